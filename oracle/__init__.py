@@ -1,0 +1,232 @@
+"""CPU FP64 oracle of the hydro step: TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  It wraps ``hydro_oracle.c`` (plain scalar C built with FMA
+contraction off) through ctypes and splits leaves over host threads; ctypes
+releases the GIL during each call, so the threads run the C code in parallel.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hydro_oracle.c")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(BUILD, "libhydro_oracle.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-lm"]
+
+NF, NC = 7, 512
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library with gcc (contraction off, IEEE FP64)."""
+    os.makedirs(BUILD, exist_ok=True)
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS[:-3], "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Phys(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("omega", C.c_double),
+                ("eta1", C.c_double), ("eta2", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        L.oracle_ppm.argtypes = [dp, dp, dp]
+        L.oracle_point_flux.argtypes = [C.c_int, dp, dp, dp, C.POINTER(Phys), dp]
+        L.oracle_point_flux.restype = C.c_double
+        L.oracle_tree_create.argtypes = [ip, ip, C.c_int, ip, ip]
+        L.oracle_tree_create.restype = C.c_void_p
+        L.oracle_tree_destroy.argtypes = [C.c_void_p]
+        L.oracle_fill_padded.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
+        L.oracle_leaf_reconstruct.argtypes = [dp, dp]
+        L.oracle_leaf_fluxes.argtypes = [dp, C.c_double, dp, C.POINTER(Phys), dp]
+        L.oracle_leaf_fluxes.restype = C.c_double
+        L.oracle_leaf_rhs.argtypes = [dp, C.c_double, dp, C.POINTER(Phys), dp, dp]
+        L.oracle_stage.argtypes = [C.c_void_p, C.c_int, C.c_double, dp, dp, dp, dp,
+                                   C.POINTER(Phys), C.c_int, C.c_int, dp, dp]
+        L.oracle_signal_speed.argtypes = [C.c_void_p, dp, dp, dp, C.POINTER(Phys),
+                                          C.c_int, C.c_int, dp]
+        L.oracle_reconstruct.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def ppm(q) -> tuple[float, float]:
+    q = _f64(q)
+    L, R = C.c_double(), C.c_double()
+    lib().oracle_ppm(_p(q), C.byref(L), C.byref(R))
+    return L.value, R.value
+
+
+def point_flux(n: int, UL, UR, xq, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
+    UL, UR, xq = _f64(UL), _f64(UR), _f64(xq)
+    F = np.zeros(7)
+    ph = Phys(gamma, omega, eta1, eta2)
+    a = lib().oracle_point_flux(int(n), _p(UL), _p(UR), _p(xq), C.byref(ph), _p(F))
+    return F, a
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+class Oracle:
+    """The oracle bound to one octree layout.
+
+    ``stage``/``step`` mirror the library's stage and step on host arrays.
+    """
+
+    def __init__(self, tree, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1, threads=None):
+        a = tree.arrays()
+        self._keep = a
+        self.n = tree.n
+        self.dx = a["dx"]
+        self.origin = a["origin"]
+        self.phys = Phys(gamma, omega, eta1, eta2)
+        self.threads = threads or default_threads()
+        ip = C.POINTER(C.c_int)
+        self._t = lib().oracle_tree_create(_p(a["nb"], C.c_int), _p(a["bc"], C.c_int), self.n,
+                                           _p(a["level"], C.c_int), _p(a["coord"], C.c_int))
+        if not self._t:
+            raise RuntimeError("oracle_tree_create failed")
+        del ip
+
+    def __del__(self):
+        t = getattr(self, "_t", None)
+        if t and _lib is not None:
+            _lib.oracle_tree_destroy(t)
+            self._t = None
+
+    def _ranges(self, l0=0, l1=None):
+        l1 = self.n if l1 is None else l1
+        k = max(1, min(self.threads, l1 - l0))
+        cuts = np.linspace(l0, l1, k + 1).astype(int)
+        return [(int(cuts[i]), int(cuts[i + 1])) for i in range(k) if cuts[i + 1] > cuts[i]]
+
+    def _run(self, fn, ranges):
+        if len(ranges) == 1:
+            rcs = [fn(*ranges[0])]
+        else:
+            with ThreadPoolExecutor(len(ranges)) as ex:
+                rcs = list(ex.map(lambda r: fn(*r), ranges))
+        if any(rcs):
+            raise RuntimeError(f"oracle call failed: {rcs}")
+
+    def padded(self, U, l0=0, l1=None):
+        U = _f64(U)
+        l1 = self.n if l1 is None else l1
+        P = np.zeros((l1 - l0, NF, 14, 14, 14))
+        rc = lib().oracle_fill_padded(self._t, _p(U), l0, l1, _p(P))
+        if rc:
+            raise RuntimeError("ghost fill failed")
+        return P
+
+    def stage(self, stage: int, dt: float, Uin, Un=None, l0=0, l1=None):
+        """One stage over leaves [l0, l1); returns (Uout, amax) for those leaves."""
+        Uin = _f64(Uin)
+        Un = Uin if Un is None else _f64(Un)
+        Uout = np.zeros_like(Uin)
+        amax = np.zeros(self.n)
+        L = lib()
+
+        def fn(a, b):
+            return L.oracle_stage(self._t, stage, float(dt), _p(Uin), _p(Un), _p(self.dx),
+                                  _p(self.origin), C.byref(self.phys), a, b, _p(Uout), _p(amax))
+        rng = self._ranges(l0, l1)
+        self._run(fn, rng)
+        l1 = self.n if l1 is None else l1
+        return Uout[l0:l1], amax[l0:l1]
+
+    def step(self, dt: float, U):
+        """Full SSP-RK2 step; returns (U_next, amax per leaf over both stages)."""
+        U1, a1 = self.stage(1, dt, U)
+        U2, a2 = self.stage(2, dt, U1, U)
+        return U2, np.maximum(a1, a2)
+
+    def signal_speed(self, U, l0=0, l1=None):
+        U = _f64(U)
+        amax = np.zeros(self.n)
+        L = lib()
+
+        def fn(a, b):
+            return L.oracle_signal_speed(self._t, _p(U), _p(self.dx), _p(self.origin),
+                                         C.byref(self.phys), a, b, _p(amax))
+        self._run(fn, self._ranges(l0, l1))
+        l1 = self.n if l1 is None else l1
+        return amax[l0:l1]
+
+    def dt(self, U, cfl=0.4):
+        a = self.signal_speed(U)
+        return float(cfl * np.min(self.dx / a))
+
+    def reconstruct(self, U, l0=0, l1=None):
+        """Reconstructed values [l1-l0][7][512][26] of interior cells."""
+        U = _f64(U)
+        l1 = self.n if l1 is None else l1
+        out = np.zeros((l1 - l0, NF, NC, 26))
+        L = lib()
+
+        def fn(a, b):
+            return L.oracle_reconstruct(self._t, _p(U), a, b, _p(out[a - l0:]))
+        self._run(fn, self._ranges(l0, l1))
+        return out
+
+
+def leaf_rhs(P, dx, origin, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
+    """L(U) [7][512] and max signal speed of one padded block [7][14][14][14]."""
+    P = _f64(P)
+    dU = np.zeros((NF, NC))
+    amax = C.c_double()
+    org = _f64(origin)
+    ph = Phys(gamma, omega, eta1, eta2)
+    lib().oracle_leaf_rhs(_p(P), float(dx), _p(org), C.byref(ph), _p(dU), C.byref(amax))
+    return dU, amax.value
+
+
+def leaf_reconstruct(P):
+    """Values at the 26 points of the interior cells of one padded block:
+    out[7][512][26] (direction order dir26)."""
+    P = _f64(P)
+    out = np.zeros((NF, NC, 26))
+    lib().oracle_leaf_reconstruct(_p(P), _p(out))
+    return out
+
+
+def leaf_fluxes(P, dx, origin, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
+    """Face fluxes [3][9][8][8][7] and max signal speed of one padded block."""
+    P = _f64(P)
+    Fn = np.zeros((3, 9, 8, 8, NF))
+    org = _f64(origin)
+    ph = Phys(gamma, omega, eta1, eta2)
+    a = lib().oracle_leaf_fluxes(_p(P), float(dx), _p(org), C.byref(ph), _p(Fn))
+    return Fn, a
+
+
+def dir26(d) -> int:
+    k = 9 * (d[2] + 1) + 3 * (d[1] + 1) + (d[0] + 1)
+    return k if k < 13 else k - 1

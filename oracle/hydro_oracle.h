@@ -1,0 +1,79 @@
+/*
+ * CPU FP64 oracle for the per-leaf hydro step of Octo-Tiger's new hydro module
+ * (arXiv 2107.10987, section IV-B).  TEST INFRASTRUCTURE ONLY: the library's
+ * tests, its smoke check and the benchmark's CPU-baseline leg call it; the
+ * product path never does.  It shares no code with the GPU library.
+ *
+ * Layouts (all host memory, caller-owned):
+ *   U        [n][7][8][8][8]  fields rho, sx, sy, sz, E, tau, X; cell [k][j][i], i fastest
+ *   P        [n][7][14][14][14] ghost-padded block, index (k+3, j+3, i+3)
+ *   dx       [n]              cell size of each leaf
+ *   origin   [n][3]           centre of cell (0,0,0) of each leaf
+ *   tree     nb[3] root leaves per axis, bc[3] (0 periodic, 1 outflow),
+ *            level[n], coord[n][3] (leaf coordinates at its level)
+ * Directions d = (dx,dy,dz) in {-1,0,1}^3 \ {0} are numbered
+ *   dir27(d) = 9(dz+1) + 3(dy+1) + (dx+1), and dir26 skips the centre (13).
+ */
+#ifndef HYDRO_ORACLE_H
+#define HYDRO_ORACLE_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double gamma;   /* ratio of specific heats */
+    double omega;   /* frame rotation rate about the z axis through x = y = 0 */
+    double eta1;    /* dual-energy pressure switch at face points */
+    double eta2;    /* dual-energy tracer resync threshold after a step */
+} oracle_phys;
+
+/* One-dimensional PPM on five equally spaced values q[0..4] = q_{-2..2}:
+ * left and right interface values of the middle cell. */
+void oracle_ppm(const double q[5], double *left, double *right);
+
+/* Central-upwind flux through a face normal to axis n at point xq from the
+ * left/right conserved states; returns the local signal speed. */
+double oracle_point_flux(int n, const double UL[7], const double UR[7], const double xq[3],
+                         const oracle_phys *ph, double F[7]);
+
+/* Tree context used for ghost filling. */
+void *oracle_tree_create(const int nb[3], const int bc[3], int n, const int *level,
+                         const int *coord);
+void oracle_tree_destroy(void *t);
+
+/* Ghost-padded blocks of leaves [l0, l1) built from U. Returns 0, or -1 when a
+ * ghost cell has no covering leaf. */
+int oracle_fill_padded(const void *t, const double *U, int l0, int l1, double *P);
+
+/* Reconstructed values at the 26 points of every interior cell of one padded
+ * block: out[7][512][26]. */
+void oracle_leaf_reconstruct(const double *P, double *out);
+
+/* Face fluxes of one leaf: Fn[3][9][8][8][7] (axis, face along the axis, the
+ * other two axes in increasing order, field); returns the max signal speed. */
+double oracle_leaf_fluxes(const double *P, double dx, const double origin[3], const oracle_phys *ph,
+                          double *Fn);
+
+/* L(U) of one leaf from its padded block: dU[7][512]; *amax = max signal speed
+ * over the leaf's face points. */
+void oracle_leaf_rhs(const double *P, double dx, const double origin[3], const oracle_phys *ph,
+                     double *dU, double *amax);
+
+/* One SSP-RK2 stage for leaves [l0, l1): stage 1: Uout = Uin + dt L(Uin);
+ * stage 2: Uout = (Un + (Uin + dt L(Uin)))/2 followed by the tracer resync.
+ * Ghosts come from Uin over the whole tree. amax[l] for l in [l0, l1). */
+int oracle_stage(const void *t, int stage, double dt, const double *Uin, const double *Un,
+                 const double *dx, const double *origin, const oracle_phys *ph,
+                 int l0, int l1, double *Uout, double *amax);
+
+/* Maximum signal speed of every leaf in [l0, l1) for the state U. */
+int oracle_signal_speed(const void *t, const double *U, const double *dx, const double *origin,
+                        const oracle_phys *ph, int l0, int l1, double *amax);
+
+/* Reconstruction of leaves [l0, l1): out[n][7][512][26]. */
+int oracle_reconstruct(const void *t, const double *U, int l0, int l1, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
