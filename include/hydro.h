@@ -1,0 +1,148 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) hydro library.
+ *
+ * The library advances the evolved fields of octree leaf subgrids by the
+ * finite-volume hydro step of Octo-Tiger's new hydro module (arXiv 2107.10987,
+ * section IV-B): PPM reconstruction at the 26 face, edge and corner points of
+ * every cell along the 13 lines through its centre, central-upwind
+ * (Kurganov-Tadmor) point fluxes with the maximum signal speed, Newton-Cotes
+ * face quadrature, flux divergence with rotating-frame sources, and a
+ * two-stage SSP Runge-Kutta update with dual-energy (entropy tracer) pressure.
+ *
+ * Data layout (device memory owned by the caller unless noted):
+ *   U         double [n][7][8][8][8]  fields rho, sx, sy, sz, E, tau, X per leaf;
+ *                                      cells [k][j][i], i fastest (structure of arrays)
+ *   dx        double [n]               cell size of each leaf
+ *   origin    double [n][3]            centre of cell (0,0,0) of each leaf; the frame
+ *                                      rotates about the z axis through x = y = 0
+ *   ghost_map int32  [n][2232]         source of every ghost cell of every leaf, in
+ *                                      raster order (k, j, i in -3..10, i fastest,
+ *                                      interior 0..7 skipped).  Entry s >= 0: copy
+ *                                      cell s%512 of leaf s/512; s < 0: mean of the
+ *                                      2x2x2 cells of leaf b/512 whose lowest cell is
+ *                                      b%512, b = -s-1.  hydro_ghost_map builds it.
+ * Every call is asynchronous on the caller's stream except where noted.
+ * Return codes: 0 on success or a negative HYDRO_E* code; nothing aborts and no
+ * C++ exception crosses this boundary.  A handle is not thread-safe; use one
+ * handle per stream.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_OK 0
+#define HYDRO_EINVAL (-1)   /* bad argument; text in hydro_last_error          */
+#define HYDRO_ENOMEM (-2)   /* workspace too small or allocation failed         */
+#define HYDRO_EHIP (-3)     /* HIP runtime error; its text in hydro_last_error  */
+#define HYDRO_ENONPHYS (-4) /* rho <= 0 or a non-finite value was produced      */
+
+#define HYDRO_NX 8          /* cells per leaf edge */
+#define HYDRO_GHOST 3       /* ghost layers: the five-point PPM stencil       */
+#define HYDRO_NF 7          /* evolved fields                                 */
+#define HYDRO_NGHOST 2232   /* ghost cells per leaf: 14^3 - 8^3               */
+
+typedef struct hydro_t hydro_t;
+
+/* Library-wide settings fixed at creation. */
+typedef struct hydro_params {
+    int32_t max_leaves; /* capacity of every workspace, in leaves (> 0)             */
+    int32_t device;     /* HIP device ordinal                                        */
+    int32_t recon;      /* 0: plain PPM reconstruction                               */
+    int32_t reserved;
+    double eta1;        /* dual energy: e < eta1*E at a point -> e = tau^gamma (1e-3) */
+    double eta2;        /* dual energy: e > eta2*E after a step -> tau = e^(1/gamma)  */
+} hydro_params;
+
+/* One set of leaves that exchange ghosts: the whole mesh of a step. */
+typedef struct hydro_grid {
+    int32_t n;                 /* leaves, 0 < n <= max_leaves                        */
+    int32_t n_launch;          /* 0: one launch per stage; else launches over the   */
+    const int32_t *launch_off; /*   host leaf ranges [launch_off[b], launch_off[b+1]) */
+    double *U;                 /* device [n][7][512], conserved state                */
+    const double *dx;          /* device [n]                                         */
+    const double *origin;      /* device [n][3]                                      */
+    const int32_t *ghost_map;  /* device [n][2232]                                   */
+    double omega;              /* frame rotation rate about z                        */
+    double gamma;              /* ratio of specific heats, > 1                       */
+    void *stream;              /* hipStream_t; NULL = the null stream                */
+} hydro_grid;
+
+/* Octree description used to build the ghost map (host memory). */
+typedef struct hydro_tree {
+    int32_t n;              /* leaves                                                */
+    int32_t nb[3];          /* level-0 leaves per axis                               */
+    int32_t bc[3];          /* per axis: 0 periodic, 1 zero-gradient outflow         */
+    const int32_t *level;   /* [n] refinement level of each leaf                     */
+    const int32_t *coord;   /* [n][3] leaf coordinates at its level                  */
+} hydro_tree;
+
+/* Allocate every workspace the step needs (state copy for the first stage,
+ * per-leaf signal speeds, error flags) for up to p->max_leaves leaves on
+ * p->device.  No later call allocates device memory.  *out is NULL on error. */
+int hydro_create(const hydro_params *p, hydro_t **out);
+
+/* Free the workspace; idempotent on NULL. */
+int hydro_destroy(hydro_t *h);
+
+/* Build the ghost map of a tree on the host into map[t->n][2232] (caller-owned
+ * host memory).  Ghost cells take: periodic wrap or zero-gradient outflow at
+ * the leaf's level; a same-level cell; the covering cell of a coarser leaf
+ * (injection); or the mean of the 2x2x2 cells of a leaf one level finer.
+ * Returns HYDRO_EINVAL if the tree is not 2:1 balanced or a leaf is outside
+ * the box.  Synchronous; needs no handle and no GPU. */
+int hydro_ghost_map(const hydro_tree *t, int32_t *map);
+
+/* One full two-stage SSP-RK2 step of all leaves, in place on g->U:
+ *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2, then the tracer resync,
+ * ghosts refreshed from the stage input before each stage (section IV-B).
+ * If amax_out (host, [g->n]) is non-NULL the call synchronises the stream,
+ * writes each leaf's maximum signal speed over both stages and reports
+ * HYDRO_ENONPHYS if a stage produced rho <= 0 or a non-finite value.  Otherwise
+ * it returns without waiting and the speeds stay in the handle
+ * (hydro_amax_device). */
+int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out);
+
+/* One stage with explicit buffers (device, [n][7][512] each; Uin provides the
+ * ghosts of every leaf).  stage 1: Uout = Uin + dt L(Uin).  stage 2:
+ * Uout = (Un + (Uin + dt L(Uin)))/2 and the tracer resync.  Uout may alias Un,
+ * not Uin.  amax (device [n], may be NULL) receives each leaf's maximum
+ * signal speed.  g->U is not used. */
+int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
+                const double *Un, double *Uout, double *amax);
+
+/* Maximum signal speed of each leaf for the state g->U: amax (device [n]). */
+int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax);
+
+/* Reconstructed values of every interior cell at its 26 points:
+ * out (device [n][7][512][26]); point d = (dx,dy,dz) is numbered
+ * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre. */
+int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out);
+
+/* Device pointer to the per-leaf maximum signal speeds of the last step. */
+const double *hydro_amax_device(const hydro_t *h);
+
+/* Synchronise the handle's last stream and report HYDRO_ENONPHYS if any
+ * stage since the previous check produced rho <= 0 or a non-finite value;
+ * clears the flag. */
+int hydro_check(hydro_t *h, void *stream);
+
+/* Stage-kernel timing.  enable = 1 starts recording a HIP event pair around
+ * every stage launch on its stream (up to 4096 launches, then recording
+ * stops); enable = 0 stops.  If total_ms / launches are non-NULL the call
+ * first waits for the recorded events and reports the summed kernel time (ms)
+ * and the number of launches timed since the previous report, then clears
+ * them.  Event objects are created on the first enable. */
+int hydro_timing(hydro_t *h, int enable, double *total_ms, int64_t *launches);
+
+const char *hydro_strerror(int code);
+const char *hydro_last_error(const hydro_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,381 @@
+// Host side of the C ABI declared in include/hydro.h: handle and workspace
+// management, argument validation, stage sequencing and the octree ghost map.
+
+#include "hydro_common.h"
+#include "../../include/hydro.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace hydro;
+
+struct hydro_t {
+    hydro_params p;
+    int device;
+    double *U1 = nullptr;      // first-stage state [max_leaves][7][512]
+    double *amax = nullptr;    // per-leaf signal speeds [max_leaves]
+    Status *status = nullptr;  // device status word
+    hipStream_t last_stream = nullptr;
+    std::string err;
+    // stage-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;          // pairs recorded since the last report
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(hydro_t *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+int hip_fail(hydro_t *h, hipError_t e, const char *what) {
+    return fail(h, HYDRO_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Padded index of each ghost slot in raster order (k, j, i over -3..10,
+// interior skipped); the same order as the ghost map.
+std::vector<uint16_t> ghost_table() {
+    std::vector<uint16_t> t;
+    t.reserve(NG);
+    for (int k = -GW; k < NX + GW; ++k)
+        for (int j = -GW; j < NX + GW; ++j)
+            for (int i = -GW; i < NX + GW; ++i) {
+                const bool in = i >= 0 && i < NX && j >= 0 && j < NX && k >= 0 && k < NX;
+                if (!in) t.push_back((uint16_t)(((k + GW) * PB + (j + GW)) * PB + (i + GW)));
+            }
+    return t;
+}
+
+std::once_flag g_table_once[64];
+hipError_t g_table_err[64];
+
+hipError_t ensure_ghost_table(int dev) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::call_once(g_table_once[dev], [dev] {
+        std::vector<uint16_t> t = ghost_table();
+        g_table_err[dev] = hydro_upload_ghost_table(t.data());
+    });
+    return g_table_err[dev];
+}
+
+int check_grid(hydro_t *h, const hydro_grid *g) {
+    if (!h) return HYDRO_EINVAL;
+    if (!g) return fail(h, HYDRO_EINVAL, "grid is NULL");
+    if (g->n <= 0) return fail(h, HYDRO_EINVAL, "grid has no leaves");
+    if (g->n > h->p.max_leaves)
+        return fail(h, HYDRO_ENOMEM, "grid has " + std::to_string(g->n) + " leaves, workspace holds " +
+                                         std::to_string(h->p.max_leaves));
+    if (!g->dx || !g->origin || !g->ghost_map) return fail(h, HYDRO_EINVAL, "null dx/origin/ghost_map");
+    if (!(g->gamma > 1.0) || !isfinite(g->gamma)) return fail(h, HYDRO_EINVAL, "gamma must be > 1");
+    if (!isfinite(g->omega)) return fail(h, HYDRO_EINVAL, "omega must be finite");
+    if (g->n_launch < 0) return fail(h, HYDRO_EINVAL, "n_launch < 0");
+    if (g->n_launch > 0) {
+        if (!g->launch_off) return fail(h, HYDRO_EINVAL, "launch_off is NULL");
+        if (g->launch_off[0] != 0 || g->launch_off[g->n_launch] != g->n)
+            return fail(h, HYDRO_EINVAL, "launch_off must run from 0 to n");
+        for (int b = 0; b < g->n_launch; ++b)
+            if (g->launch_off[b + 1] < g->launch_off[b])
+                return fail(h, HYDRO_EINVAL, "launch_off must be non-decreasing");
+    }
+    return HYDRO_OK;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+int set_device(hydro_t *h) {
+    hipError_t e = hipSetDevice(h->device);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "hipSetDevice");
+}
+
+// Launch one stage over all leaves, split as the grid asks.
+int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
+              const double *Un, double *Uout, double *amax, int accumulate) {
+    StageArgs a;
+    a.Uin = Uin;
+    a.Un = Un;
+    a.Uout = Uout;
+    a.dx = g->dx;
+    a.origin = g->origin;
+    a.gmap = g->ghost_map;
+    a.amax = amax;
+    a.status = h->status;
+    a.ph = Phys{g->gamma, g->omega, h->p.eta1, h->p.eta2};
+    a.dt = dt;
+    a.stage = stage;
+    a.amax_accumulate = accumulate;
+    hipStream_t s = (hipStream_t)g->stream;
+    h->last_stream = s;
+    const int nb = g->n_launch > 0 ? g->n_launch : 1;
+    for (int b = 0; b < nb; ++b) {
+        a.leaf0 = g->n_launch > 0 ? g->launch_off[b] : 0;
+        a.nleaf = g->n_launch > 0 ? g->launch_off[b + 1] - a.leaf0 : g->n;
+        if (a.nleaf == 0) continue;
+        const bool rec = h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
+        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], s);
+        hipError_t e = hydro_launch_stage(a, s);
+        if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used++ + 1], s);
+    }
+    return HYDRO_OK;
+}
+
+int read_status(hydro_t *h, hipStream_t s) {
+    Status st;
+    hipError_t e = hipMemcpyAsync(&st, h->status, sizeof(Status), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "status read");
+    if (st.flag) {
+        e = hipMemsetAsync(h->status, 0, sizeof(Status), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "status reset");
+        static const char *names[NF] = {"rho", "sx", "sy", "sz", "egas", "tau", "spc"};
+        char buf[160];
+        snprintf(buf, sizeof buf, "non-physical %s at leaf %d cell %d",
+                 (st.field >= 0 && st.field < NF) ? names[st.field] : "value", st.leaf, st.cell);
+        return fail(h, HYDRO_ENONPHYS, buf);
+    }
+    return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_create(const hydro_params *p, hydro_t **out) {
+    if (!out) return fail(nullptr, HYDRO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, HYDRO_EINVAL, "params is NULL");
+    if (p->max_leaves <= 0) return fail(nullptr, HYDRO_EINVAL, "max_leaves must be > 0");
+    if (p->recon != 0) return fail(nullptr, HYDRO_EINVAL, "recon must be 0 (plain PPM)");
+    if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
+    hydro_t *h = new (std::nothrow) hydro_t();
+    if (!h) return fail(nullptr, HYDRO_ENOMEM, "handle allocation");
+    h->p = *p;
+    h->device = p->device;
+    int rc = set_device(h);
+    if (rc) { g_create_err = h->err; delete h; return rc; }
+    hipError_t e = ensure_ghost_table(h->device);
+    if (e != hipSuccess) { rc = hip_fail(h, e, "ghost table upload"); g_create_err = h->err; delete h; return rc; }
+    const size_t n = (size_t)p->max_leaves;
+    e = hipMalloc((void **)&h->U1, n * LEAF_STRIDE * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->amax, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->status, sizeof(Status));
+    if (e == hipSuccess) e = hipMemset(h->status, 0, sizeof(Status));
+    if (e == hipSuccess) e = hipMemset(h->amax, 0, n * sizeof(double));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        rc = (e == hipErrorOutOfMemory) ? fail(h, HYDRO_ENOMEM, "workspace allocation")
+                                        : hip_fail(h, e, "workspace allocation");
+        g_create_err = h->err;
+        hydro_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return HYDRO_OK;
+}
+
+int hydro_destroy(hydro_t *h) {
+    if (!h) return HYDRO_OK;
+    (void)hipSetDevice(h->device);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->U1) (void)hipFree(h->U1);
+    if (h->amax) (void)hipFree(h->amax);
+    if (h->status) (void)hipFree(h->status);
+    delete h;
+    return HYDRO_OK;
+}
+
+int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !aligned8(g->U)) return fail(h, HYDRO_EINVAL, "U is NULL or misaligned");
+    if (!(dt >= 0.0) || !isfinite(dt)) return fail(h, HYDRO_EINVAL, "dt must be finite and >= 0");
+    if ((rc = set_device(h))) return rc;
+    if ((rc = run_stage(h, g, 1, dt, g->U, g->U, h->U1, h->amax, 0))) return rc;
+    if ((rc = run_stage(h, g, 2, dt, h->U1, g->U, g->U, h->amax, 1))) return rc;
+    if (amax_out) {
+        hipStream_t s = (hipStream_t)g->stream;
+        hipError_t e = hipMemcpyAsync(amax_out, h->amax, sizeof(double) * g->n, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(h, e, "amax copy");
+        return read_status(h, s);
+    }
+    return HYDRO_OK;
+}
+
+int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
+                const double *Un, double *Uout, double *amax) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (stage != 1 && stage != 2) return fail(h, HYDRO_EINVAL, "stage must be 1 or 2");
+    if (!Uin || !Uout || (stage == 2 && !Un)) return fail(h, HYDRO_EINVAL, "null stage buffer");
+    if (!aligned8(Uin) || !aligned8(Uout) || (Un && !aligned8(Un)))
+        return fail(h, HYDRO_EINVAL, "stage buffers must be 8-byte aligned");
+    if (Uin == Uout) return fail(h, HYDRO_EINVAL, "Uout may not alias Uin");
+    if (!(dt >= 0.0) || !isfinite(dt)) return fail(h, HYDRO_EINVAL, "dt must be finite and >= 0");
+    if ((rc = set_device(h))) return rc;
+    return run_stage(h, g, stage, dt, Uin, stage == 2 ? Un : Uin, Uout, amax, 0);
+}
+
+int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !amax) return fail(h, HYDRO_EINVAL, "null U or amax");
+    if ((rc = set_device(h))) return rc;
+    return run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, amax, 0);
+}
+
+int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !out) return fail(h, HYDRO_EINVAL, "null U or out");
+    if ((rc = set_device(h))) return rc;
+    hipError_t e = hydro_launch_reconstruct(g->U, g->ghost_map, g->n, out, (hipStream_t)g->stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "reconstruct launch");
+}
+
+const double *hydro_amax_device(const hydro_t *h) { return h ? h->amax : nullptr; }
+
+int hydro_check(hydro_t *h, void *stream) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = set_device(h);
+    if (rc) return rc;
+    return read_status(h, (hipStream_t)stream);
+}
+
+int hydro_timing(hydro_t *h, int enable, double *total_ms, int64_t *launches) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (total_ms || launches) {
+        double ms = 0.0;
+        for (size_t i = 0; i < h->ev_used; ++i) {
+            hipError_t e = hipEventSynchronize(h->ev[2 * i + 1]);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1]);
+            if (e != hipSuccess) return hip_fail(h, e, "event timing");
+            ms += t;
+        }
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = (int64_t)h->ev_used;
+        h->ev_used = 0;
+    }
+    if (enable && h->ev.empty()) {
+        h->ev.resize(2 * 4096);
+        for (auto &e : h->ev) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return hip_fail(h, err, "hipEventCreate");
+        }
+    }
+    h->timing = enable != 0;
+    return HYDRO_OK;
+}
+
+const char *hydro_strerror(int code) {
+    switch (code) {
+    case HYDRO_OK: return "ok";
+    case HYDRO_EINVAL: return "invalid argument";
+    case HYDRO_ENOMEM: return "out of workspace or device memory";
+    case HYDRO_EHIP: return "HIP runtime error";
+    case HYDRO_ENONPHYS: return "non-physical state";
+    default: return "unknown error";
+    }
+}
+
+const char *hydro_last_error(const hydro_t *h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Ghost map of an octree (host)
+// ---------------------------------------------------------------------------
+
+int hydro_ghost_map(const hydro_tree *t, int32_t *map) {
+    if (!t || !map || !t->level || !t->coord || t->n <= 0)
+        return fail(nullptr, HYDRO_EINVAL, "null or empty tree");
+    if ((int64_t)t->n * NC > INT32_MAX) return fail(nullptr, HYDRO_EINVAL, "too many leaves for int32 cell ids");
+    for (int a = 0; a < 3; ++a)
+        if (t->nb[a] <= 0 || (t->bc[a] != 0 && t->bc[a] != 1))
+            return fail(nullptr, HYDRO_EINVAL, "bad nb/bc");
+    int lmax = 0;
+    for (int i = 0; i < t->n; ++i) {
+        if (t->level[i] < 0 || t->level[i] > 20) return fail(nullptr, HYDRO_EINVAL, "level out of range");
+        lmax = t->level[i] > lmax ? t->level[i] : lmax;
+    }
+    auto key = [](int l, int64_t x, int64_t y, int64_t z) -> uint64_t {
+        return ((uint64_t)l << 60) | ((uint64_t)z << 40) | ((uint64_t)y << 20) | (uint64_t)x;
+    };
+    std::unordered_map<uint64_t, int32_t> owner;
+    owner.reserve((size_t)t->n * 2);
+    for (int i = 0; i < t->n; ++i) {
+        const int32_t *c = t->coord + 3 * (size_t)i;
+        const int l = t->level[i];
+        for (int a = 0; a < 3; ++a)
+            if (c[a] < 0 || (int64_t)c[a] >= ((int64_t)t->nb[a] << l))
+                return fail(nullptr, HYDRO_EINVAL, "leaf outside the box");
+        if (!owner.emplace(key(l, c[0], c[1], c[2]), i).second)
+            return fail(nullptr, HYDRO_EINVAL, "duplicate leaf");
+    }
+    auto find = [&](int l, const int64_t g[3]) -> int32_t {
+        auto it = owner.find(key(l, g[0] >> 3, g[1] >> 3, g[2] >> 3));
+        return it == owner.end() ? -1 : it->second;
+    };
+    auto local = [](const int64_t g[3]) -> int32_t {
+        return (int32_t)(((g[2] & 7) * NX + (g[1] & 7)) * NX + (g[0] & 7));
+    };
+    for (int i = 0; i < t->n; ++i) {
+        const int l = t->level[i];
+        const int32_t *c = t->coord + 3 * (size_t)i;
+        int32_t *m = map + (size_t)i * NG;
+        int s = 0;
+        for (int k = -GW; k < NX + GW; ++k)
+            for (int j = -GW; j < NX + GW; ++j)
+                for (int ii = -GW; ii < NX + GW; ++ii) {
+                    if (ii >= 0 && ii < NX && j >= 0 && j < NX && k >= 0 && k < NX) continue;
+                    const int off[3] = {ii, j, k};
+                    int64_t g[3];
+                    for (int a = 0; a < 3; ++a) {
+                        const int64_t nc = (int64_t)NX * t->nb[a] << l;
+                        int64_t v = (int64_t)NX * c[a] + off[a];
+                        if (v < 0 || v >= nc) {
+                            if (t->bc[a] == 0) v = ((v % nc) + nc) % nc;
+                            else v = v < 0 ? 0 : nc - 1;
+                        }
+                        g[a] = v;
+                    }
+                    int32_t src = -1;
+                    bool found = false;
+                    // a leaf at this level or coarser covering the cell
+                    for (int lc = l; lc >= 0 && !found; --lc) {
+                        const int64_t gc[3] = {g[0] >> (l - lc), g[1] >> (l - lc), g[2] >> (l - lc)};
+                        const int32_t o = find(lc, gc);
+                        if (o >= 0) {
+                            src = o * NC + local(gc);
+                            found = true;
+                        }
+                    }
+                    if (!found) {
+                        // refined: its 2x2x2 children must belong to one leaf of level l+1
+                        const int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
+                        const int32_t o = (l < lmax) ? find(l + 1, gf) : -1;
+                        if (o < 0)
+                            return fail(nullptr, HYDRO_EINVAL,
+                                        "ghost cell of leaf " + std::to_string(i) +
+                                            " is neither covered nor refined once (tree not 2:1 balanced)");
+                        src = -(o * NC + local(gf)) - 1;
+                    }
+                    m[s++] = src;
+                }
+    }
+    return HYDRO_OK;
+}
+
+}  // extern "C"

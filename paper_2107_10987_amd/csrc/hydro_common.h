@@ -1,0 +1,60 @@
+// Shared definitions of the gfx950 hydro library (device and host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hydro {
+
+constexpr int NX = 8;                      // cells per leaf edge
+constexpr int GW = 3;                      // ghost layers
+constexpr int PB = NX + 2 * GW;            // padded edge: 14
+constexpr int NF = 7;                      // rho, sx, sy, sz, E, tau, X
+constexpr int NC = NX * NX * NX;           // 512 interior cells
+constexpr int NP = PB * PB * PB;           // 2744 padded cells
+constexpr int NG = NP - NC;                // 2232 ghost cells
+constexpr int FACES_PER_AXIS = (NX + 1) * NX * NX;  // 576
+constexpr int NFACE = 3 * FACES_PER_AXIS;           // 1728
+constexpr int LEAF_STRIDE = NF * NC;                // doubles per leaf in U
+
+enum Field { RHO = 0, SX = 1, SY = 2, SZ = 3, EGAS = 4, TAU = 5, SPC = 6 };
+
+struct Phys {
+    double gamma;
+    double omega;
+    double eta1;
+    double eta2;
+};
+
+// Non-physical result report written by the stage kernels.
+struct Status {
+    int flag;       // 0 ok, 1 non-physical value produced
+    int leaf;
+    int cell;
+    int field;
+};
+
+struct StageArgs {
+    const double *Uin;        // [n][7][512] stage input (ghost source)
+    const double *Un;         // [n][7][512] step start (stage 2)
+    double *Uout;             // [n][7][512]
+    const double *dx;         // [n]
+    const double *origin;     // [n][3]
+    const int32_t *gmap;      // [n][2232]
+    double *amax;             // [n] or null
+    Status *status;
+    Phys ph;
+    double dt;
+    int leaf0;                // first leaf of this launch
+    int nleaf;                // leaves in this launch
+    int stage;                // 1, 2; 0 = signal speed only
+    int amax_accumulate;      // stage 2 of a step: amax = max(amax, this stage)
+};
+
+}  // namespace hydro
+
+// Launchers implemented in the kernel translation unit.
+hipError_t hydro_upload_ghost_table(const uint16_t *table);
+hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
+hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,
+                                    hipStream_t s);

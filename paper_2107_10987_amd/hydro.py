@@ -1,0 +1,194 @@
+"""Thin ctypes binding of the gfx950 hydro library (include/hydro.h).
+
+Argument marshalling only: every step of the hydro update runs in the HIP
+kernels of ``libhydro.so``.  PyTorch supplies device memory and streams.
+There is no CPU fallback: if the built library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libhydro.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENONPHYS = 0, -1, -2, -3, -4
+NX, NF, NC, NGHOST = 8, 7, 512, 2232
+
+EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_step", "hydro_stage",
+           "hydro_signal_speed", "hydro_reconstruct", "hydro_amax_device", "hydro_check",
+           "hydro_timing", "hydro_strerror", "hydro_last_error")
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
+                ("reserved", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_launch", C.c_int32), ("launch_off", C.POINTER(C.c_int32)),
+                ("U", C.c_void_p), ("dx", C.c_void_p), ("origin", C.c_void_p),
+                ("ghost_map", C.c_void_p), ("omega", C.c_double), ("gamma", C.c_double),
+                ("stream", C.c_void_p)]
+
+
+class Tree(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nb", C.c_int32 * 3), ("bc", C.c_int32 * 3),
+                ("level", C.POINTER(C.c_int32)), ("coord", C.POINTER(C.c_int32))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libhydro.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP hydro library not built: {path} is missing "
+                           "(run paper_2107_10987_amd/build.py)")
+    L = C.CDLL(path)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    L.hydro_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+    L.hydro_destroy.argtypes = [vp]
+    L.hydro_ghost_map.argtypes = [C.POINTER(Tree), C.POINTER(C.c_int32)]
+    L.hydro_step.argtypes = [vp, C.POINTER(Grid), C.c_double, dp]
+    L.hydro_stage.argtypes = [vp, C.POINTER(Grid), C.c_int, C.c_double, vp, vp, vp, vp]
+    L.hydro_signal_speed.argtypes = [vp, C.POINTER(Grid), vp]
+    L.hydro_reconstruct.argtypes = [vp, C.POINTER(Grid), vp]
+    L.hydro_amax_device.argtypes = [vp]
+    L.hydro_amax_device.restype = vp
+    L.hydro_check.argtypes = [vp, vp]
+    L.hydro_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.hydro_strerror.argtypes = [C.c_int]
+    L.hydro_strerror.restype = C.c_char_p
+    L.hydro_last_error.argtypes = [vp]
+    L.hydro_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype or C.c_int
+    L.hydro_amax_device.restype = vp
+    L.hydro_strerror.restype = C.c_char_p
+    L.hydro_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def ghost_map(tree) -> np.ndarray:
+    """Ghost map int32 [n][2232] of a workloads.Tree, built by the library."""
+    L = load()
+    a = tree.arrays()
+    t = Tree(tree.n, (C.c_int32 * 3)(*a["nb"]), (C.c_int32 * 3)(*a["bc"]),
+             a["level"].ctypes.data_as(C.POINTER(C.c_int32)),
+             a["coord"].ctypes.data_as(C.POINTER(C.c_int32)))
+    out = np.empty((tree.n, NGHOST), dtype=np.int32)
+    rc = L.hydro_ghost_map(C.byref(t), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
+    return out
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Hydro:
+    """A library handle: owns the device workspace for up to ``max_leaves``."""
+
+    def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.device = device
+        self.p = Params(int(max_leaves), int(device), 0, 0, float(eta1), float(eta2))
+        h = C.c_void_p()
+        rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
+        if rc:
+            raise HydroError(rc, self.L.hydro_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hydro_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc:
+            raise HydroError(rc, self.L.hydro_last_error(self.h).decode())
+
+    # -- grids ---------------------------------------------------------------
+    def grid(self, tree, U, omega: float, gamma: float, launch_off=None, stream=None,
+             gmap=None) -> "DeviceGrid":
+        return DeviceGrid(self, tree, U, omega, gamma, launch_off, stream, gmap)
+
+    # -- calls ---------------------------------------------------------------
+    def step(self, g: "DeviceGrid", dt: float, want_amax: bool = True):
+        if want_amax:
+            out = np.empty(g.n, dtype=np.float64)
+            self._check(self.L.hydro_step(self.h, C.byref(g.c), float(dt),
+                                          out.ctypes.data_as(C.POINTER(C.c_double))))
+            return out
+        self._check(self.L.hydro_step(self.h, C.byref(g.c), float(dt), None))
+        return None
+
+    def stage(self, g: "DeviceGrid", stage: int, dt: float, Uin, Un, Uout, amax=None):
+        self._check(self.L.hydro_stage(self.h, C.byref(g.c), int(stage), float(dt), _ptr(Uin),
+                                       _ptr(Un), _ptr(Uout), _ptr(amax)))
+
+    def signal_speed(self, g: "DeviceGrid"):
+        a = self.torch.empty(g.n, dtype=self.torch.float64, device=g.U.device)
+        self._check(self.L.hydro_signal_speed(self.h, C.byref(g.c), _ptr(a)))
+        return a
+
+    def reconstruct(self, g: "DeviceGrid"):
+        out = self.torch.empty((g.n, NF, NC, 26), dtype=self.torch.float64, device=g.U.device)
+        self._check(self.L.hydro_reconstruct(self.h, C.byref(g.c), _ptr(out)))
+        return out
+
+    def check(self, stream=None):
+        self._check(self.L.hydro_check(self.h, stream))
+
+    def timing(self, enable: bool = True):
+        """Start/stop stage-kernel event timing; returns (ms, launches)
+        recorded since the previous call."""
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.L.hydro_timing(self.h, int(enable), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+class DeviceGrid:
+    """Device-resident mesh of one step: U, dx, origin and ghost map as torch
+    tensors, plus the C struct that points at them."""
+
+    def __init__(self, hy: Hydro, tree, U, omega, gamma, launch_off=None, stream=None, gmap=None):
+        torch = hy.torch
+        dev = torch.device("cuda", hy.device)
+        a = tree.arrays()
+        self.n = tree.n
+        self.U = U if isinstance(U, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(U), device=dev)
+        assert self.U.dtype == torch.float64 and self.U.is_contiguous()
+        assert tuple(self.U.shape) == (tree.n, NF, NX, NX, NX)
+        self.dx = torch.as_tensor(a["dx"], device=dev)
+        self.origin = torch.as_tensor(a["origin"], device=dev)
+        gm = ghost_map(tree) if gmap is None else gmap
+        self.gmap = torch.as_tensor(gm, device=dev)
+        self.stream = stream
+        if launch_off is not None:
+            self._off = np.ascontiguousarray(launch_off, dtype=np.int32)
+            nl, offp = len(self._off) - 1, self._off.ctypes.data_as(C.POINTER(C.c_int32))
+        else:
+            self._off, nl, offp = None, 0, None
+        s = 0 if stream is None else int(stream.cuda_stream)
+        self.c = Grid(tree.n, nl, offp, _ptr(self.U), _ptr(self.dx), _ptr(self.origin),
+                      _ptr(self.gmap), float(omega), float(gamma), s or None)

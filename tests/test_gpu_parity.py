@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle on
+identical seeded inputs.
+
+Tolerance (FP64): per field f, max |gpu - oracle| / max(max |oracle_f|, 1e-300)
+<= 1e-12, the bound the build is held to; both sides evaluate the same
+expressions with contraction off, so most results agree to the last bit."""
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd.workloads import (blast_single_leaf, rotating_polytrope, sedov_uniform,
+                                            uneven_batches)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hy(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    h = Hydro(max_leaves=4096)
+    yield h
+    h.close()
+
+
+def field_err(g, o):
+    g = np.asarray(g).reshape(g.shape[0], 7, -1)
+    o = np.asarray(o).reshape(o.shape[0], 7, -1)
+    out = []
+    for f in range(7):
+        scale = max(np.abs(o[:, f]).max(), 1e-300)
+        out.append(np.abs(g[:, f] - o[:, f]).max() / scale)
+    return np.array(out)
+
+
+def _oracle(w, threads=None):
+    import oracle
+    return oracle.Oracle(w.tree, w.gamma, w.omega, threads=threads)
+
+
+def _grid(hy, torch, w, U=None, launch_off=None):
+    U = w.U if U is None else U
+    return hy.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma, launch_off=launch_off)
+
+
+def test_signal_speed_and_one_step_blast(hy, torch):
+    print("case: blast-1leaf one step", flush=True)
+    w = blast_single_leaf()
+    o = _oracle(w)
+    g = _grid(hy, torch, w)
+    a_gpu = hy.signal_speed(g).cpu().numpy()
+    a_ora = o.signal_speed(w.U)
+    assert np.abs(a_gpu - a_ora).max() <= TOL * a_ora.max()
+    dt = float(0.4 * w.tree.dx[0] / a_ora[0])
+    amax = hy.step(g, dt)
+    U_ora, am_ora = o.step(dt, w.U)
+    err = field_err(g.U.cpu().numpy(), U_ora)
+    print("blast max rel err per field", err, flush=True)
+    assert np.all(err <= TOL), err
+    assert np.abs(amax - am_ora).max() <= TOL * am_ora.max()
+
+
+def test_stage_parity_sedov64(hy, torch):
+    print("case: sedov-64^3 stages", flush=True)
+    w = sedov_uniform(8)
+    o = _oracle(w)
+    g = _grid(hy, torch, w)
+    dt = o.dt(w.U)
+    U1_ora, a1 = o.stage(1, dt, w.U)
+    U2_ora, a2 = o.stage(2, dt, U1_ora, w.U)
+    Uin = torch.tensor(w.U, device="cuda")
+    U1 = torch.empty_like(Uin)
+    am = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    hy.stage(g, 1, dt, Uin, None, U1, am)
+    assert np.all(field_err(U1.cpu().numpy(), U1_ora) <= TOL)
+    assert np.abs(am.cpu().numpy() - a1).max() <= TOL * a1.max()
+    # stage 2 from the oracle's stage-1 state: identical inputs
+    U1o = torch.tensor(U1_ora, device="cuda")
+    U2 = torch.empty_like(Uin)
+    hy.stage(g, 2, dt, U1o, Uin, U2, am)
+    err = field_err(U2.cpu().numpy(), U2_ora)
+    print("sedov stage-2 max rel err per field", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+def test_trajectory_sedov64_20_steps(hy, torch):
+    # the benchmarked workload: 64^3 Sedov as 512 leaves, 20 SSP-RK2 steps at
+    # CFL 0.4; both sides take the same dt sequence (from the oracle)
+    print("case: sedov-64^3 20-step trajectory", flush=True)
+    w = sedov_uniform(8)
+    o = _oracle(w)
+    g = _grid(hy, torch, w)
+    U = w.U.copy()
+    dt = o.dt(U)
+    worst = np.zeros(7)
+    for s in range(20):
+        amax_gpu = hy.step(g, dt)
+        U, am = o.step(dt, U)
+        err = field_err(g.U.cpu().numpy(), U)
+        worst = np.maximum(worst, err)
+        assert np.all(err <= TOL), (s, err)
+        assert np.abs(amax_gpu - am).max() <= TOL * am.max()
+        dt = float(w.cfl * np.min(w.tree.dx / am))
+    print("sedov 20-step worst rel err per field", worst, flush=True)
+
+
+def test_reconstruct_parity(hy, torch):
+    print("case: reconstruction blast + sedov-32^3", flush=True)
+    for w in (blast_single_leaf(), sedov_uniform(4)):
+        o = _oracle(w)
+        U = w.U.copy()
+        if w.n > 1:   # move the blast a little so the limiter is exercised everywhere
+            U, _ = o.step(o.dt(U), U)
+            U, _ = o.step(o.dt(U), U)
+        g = _grid(hy, torch, w, U)
+        r_gpu = hy.reconstruct(g).cpu().numpy()
+        r_ora = o.reconstruct(U)
+        for f in range(7):
+            scale = max(np.abs(r_ora[:, f]).max(), 1e-300)
+            assert np.abs(r_gpu[:, f] - r_ora[:, f]).max() <= TOL * scale, (w.name, f)
+
+
+def test_polytrope_amr_rotating_step_uneven_launches(hy, torch):
+    # 4096-leaf, 3-level octree, Omega = 0.1, launched as seeded uneven batches
+    print("case: polytrope-4096 AMR one step, uneven launches", flush=True)
+    w = rotating_polytrope()
+    off = uneven_batches(w.n)
+    o = _oracle(w)
+    g = _grid(hy, torch, w, launch_off=off)
+    dt = o.dt(w.U)
+    amax = hy.step(g, dt)
+    U_ora, am = o.step(dt, w.U)
+    err = field_err(g.U.cpu().numpy(), U_ora)
+    print("polytrope max rel err per field", err, "launches", len(off) - 1, flush=True)
+    assert np.all(err <= TOL), err
+    assert np.abs(amax - am).max() <= TOL * am.max()
+
+
+def test_launch_partition_is_bitwise_neutral(hy, torch):
+    print("case: launch partitions bitwise", flush=True)
+    w = sedov_uniform(4)
+    dt = 1e-4
+    ga = _grid(hy, torch, w)
+    gb = _grid(hy, torch, w, launch_off=np.array([0, 1, 2, 7, 30, 31, 64], np.int32))
+    hy.step(ga, dt)
+    hy.step(gb, dt)
+    assert torch.equal(ga.U, gb.U)
+
+
+def test_deterministic(hy, torch):
+    w = sedov_uniform(4)
+    ga, gb = _grid(hy, torch, w), _grid(hy, torch, w)
+    for _ in range(3):
+        hy.step(ga, 2e-4)
+        hy.step(gb, 2e-4)
+    assert torch.equal(ga.U, gb.U)
+
+
+def test_errors(hy, torch):
+    from paper_2107_10987_amd import hydro as H
+    print("case: error paths", flush=True)
+    w = sedov_uniform(4)
+    g = _grid(hy, torch, w)
+    with pytest.raises(H.HydroError) as e:
+        hy.stage(g, 3, 1e-4, g.U, g.U, torch.empty_like(g.U))
+    assert e.value.code == H.EINVAL
+    with pytest.raises(H.HydroError) as e:
+        hy.stage(g, 1, 1e-4, g.U, None, g.U)          # Uout aliases Uin
+    assert e.value.code == H.EINVAL
+    with pytest.raises(H.HydroError) as e:
+        hy.step(g, float("nan"))
+    assert e.value.code == H.EINVAL
+    bad = _grid(hy, torch, w)
+    bad.c.gamma = 1.0
+    with pytest.raises(H.HydroError) as e:
+        hy.step(bad, 1e-4)
+    assert e.value.code == H.EINVAL
+    small = H.Hydro(max_leaves=8)
+    try:
+        with pytest.raises(H.HydroError) as e:
+            small.step(_grid(small, torch, w), 1e-4)
+        assert e.value.code == H.ENOMEM
+    finally:
+        small.close()
+
+
+def test_nonphysical_state_reported(hy, torch):
+    print("case: non-physical input", flush=True)
+    from paper_2107_10987_amd import hydro as H
+    w = blast_single_leaf()
+    U = w.U.copy()
+    U[0, 0, 2, 2, 2] = -1.0
+    g = _grid(hy, torch, w, U)
+    with pytest.raises(H.HydroError) as e:
+        hy.step(g, 1e-3)
+    assert e.value.code == H.ENONPHYS
+    # the flag is cleared: a good state steps cleanly afterwards
+    g2 = _grid(hy, torch, w)
+    hy.step(g2, 1e-3)

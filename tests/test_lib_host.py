@@ -1,0 +1,112 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the shared library
+loads and exports every function include/hydro.h declares, error codes and
+messages are stable, and the ghost map built by the library reproduces the
+oracle's ghost layers exactly when applied on the host."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd import hydro
+from paper_2107_10987_amd.build import LIB
+from paper_2107_10987_amd.workloads import (OUTFLOW, PERIODIC, LeafSet, blast_single_leaf,
+                                            rotating_polytrope, sedov_uniform, uniform_tree)
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hydro.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libhydro.so not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
+
+
+@needs_lib
+def test_exports_every_declared_symbol():
+    L = hydro.load()
+    decl = declared_functions()
+    assert set(decl) == set(hydro.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+@needs_lib
+def test_strerror_codes():
+    L = hydro.load()
+    assert L.hydro_strerror(0) == b"ok"
+    assert L.hydro_strerror(-1) == b"invalid argument"
+    assert L.hydro_strerror(-4) == b"non-physical state"
+    assert L.hydro_strerror(99) == b"unknown error"
+
+
+@needs_lib
+@pytest.mark.parametrize("make", ["blast", "sedov32", "amr_out", "amr_per", "polytrope"])
+def test_ghost_map_matches_oracle(oracle_mod, make):
+    if make == "blast":
+        w = blast_single_leaf()
+        tree, U = w.tree, w.U
+    elif make == "sedov32":
+        w = sedov_uniform(4)
+        tree, U = w.tree, w.U
+    elif make == "polytrope":
+        w = rotating_polytrope()
+        tree, U = w.tree, w.U
+    else:
+        bc = (OUTFLOW,) * 3 if make == "amr_out" else (PERIODIC, OUTFLOW, PERIODIC)
+        ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / 16,
+                     [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+        ls.refine(0, (0, 0, 0))
+        if ls.can_refine(1, (0, 0, 0)):
+            ls.refine(1, (0, 0, 0))
+        tree = ls.tree()
+        U = np.random.default_rng(4).uniform(0.5, 2.0, (tree.n, 7, 8, 8, 8))
+    gm = hydro.ghost_map(tree)
+    assert gm.shape == (tree.n, 2232)
+    o = oracle_mod.Oracle(tree)
+    n = min(tree.n, 600)
+    assert np.array_equal(_apply_map_subset(U, gm, n), o.padded(U, 0, n))
+
+
+def _apply_map_subset(U, gm, n):
+    n_all = U.shape[0]
+    flat = U.reshape(n_all, 7, 512)
+    r = np.arange(-3, 11)
+    K, J, I = np.meshgrid(r, r, r, indexing="ij")
+    ghost = ~((I >= 0) & (I < 8) & (J >= 0) & (J < 8) & (K >= 0) & (K < 8))
+    gidx = np.nonzero(ghost.ravel())[0]
+    P = np.zeros((n, 7, 14 ** 3))
+    for l in range(n):
+        P[l][:, ~ghost.ravel()] = flat[l]
+        s = gm[l]
+        cp = s >= 0
+        src = s[cp]
+        P[l][:, gidx[cp]] = flat[src // 512, :, src % 512].T
+        b = -s[~cp] - 1
+        if b.size:
+            acc = np.zeros((7, b.size))
+            for off in (0, 1, 8, 9, 64, 65, 72, 73):
+                acc = acc + flat[b // 512, :, b % 512 + off].T
+            P[l][:, gidx[~cp]] = acc * 0.125
+    return P.reshape(n, 7, 14, 14, 14)
+
+
+@needs_lib
+def test_ghost_map_rejects_unbalanced_tree():
+    ls = LeafSet((2, 2, 2), (OUTFLOW,) * 3, (0, 0, 0), 1 / 16,
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+    ls.refine(0, (0, 0, 0))
+    ls.refine(1, (1, 1, 1))        # level-2 leaves next to level-0 leaves
+    with pytest.raises(hydro.HydroError) as e:
+        hydro.ghost_map(ls.tree())
+    assert e.value.code == hydro.EINVAL
+
+
+@needs_lib
+def test_ghost_map_rejects_bad_tree():
+    t = uniform_tree((2, 1, 1), (PERIODIC,) * 3)
+    t.coord[1, 0] = 5               # outside the box
+    with pytest.raises(hydro.HydroError):
+        hydro.ghost_map(t)
