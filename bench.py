@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--schedule", default="column", choices=["column", "face"])
     return ap.parse_args()
 
 
@@ -87,7 +88,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     w = sedov_uniform(8)
-    hy = Hydro(max_leaves=w.n)
+    hy = Hydro(max_leaves=w.n, schedule=args.schedule)
     U0 = torch.tensor(w.U, device="cuda")
     g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma)
     dxs = w.tree.dx
@@ -134,7 +135,8 @@ def main():
         "config": {"workload": "sedov-64^3: 512 leaves of 8^3 cells + 3 ghost layers, FP64, gamma 5/3, "
                                "outflow, SSP-RK2 at CFL 0.4, plain PPM, one leaf per workgroup",
                    "leaves": w.n, "cells": w.cells, "stages_per_step": 2, "path": "plain"},
-        "kernel": {"name": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
+        "kernel": {"name": "stage_kernel_col" if args.schedule == "column" else "stage_kernel",
+                   "schedule": args.schedule, "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
                    "kernel_cell_updates_per_s": cells_per_launch / avg_launch_s},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None},

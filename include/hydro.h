@@ -48,14 +48,24 @@ extern "C" {
 
 typedef struct hydro_t hydro_t;
 
+/* Stage-kernel schedules (hydro_params.schedule). */
+#define HYDRO_SCHED_AUTO 0        /* per launch size: the autotuned table, else a built-in rule  */
+#define HYDRO_SCHED_FACE 1        /* a workgroup per leaf, one face of each axis per thread       */
+#define HYDRO_SCHED_COLUMN 2      /* a workgroup per leaf, lanes walk cell columns (1.71x PPM)    */
+#define HYDRO_SCHED_PERSISTENT 3  /* one workgroup per compute unit pulling leaves from a queue  */
+#define HYDRO_SCHED_TILED 4       /* persistent, queue of (leaf, axis) items: 3x the parallelism */
+#define HYDRO_NBUCKET 16          /* autotune buckets: launch size in [2^b, 2^(b+1))             */
+
 /* Library-wide settings fixed at creation. */
 typedef struct hydro_params {
     int32_t max_leaves; /* capacity of every workspace, in leaves (> 0)             */
     int32_t device;     /* HIP device ordinal                                        */
     int32_t recon;      /* 0: plain PPM reconstruction                               */
-    int32_t reserved;
+    int32_t schedule;   /* HYDRO_SCHED_*                                             */
     double eta1;        /* dual energy: e < eta1*E at a point -> e = tau^gamma (1e-3) */
     double eta2;        /* dual energy: e > eta2*E after a step -> tau = e^(1/gamma)  */
+    const char *tune_cache; /* NULL, or a JSON table written by hydro_autotune: loaded
+                               at creation and used by HYDRO_SCHED_AUTO            */
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */
@@ -82,6 +92,7 @@ typedef struct hydro_tree {
 } hydro_tree;
 
 /* Allocate every workspace the step needs (state copy for the first stage,
+ * per-leaf flux differences of the column-walk schedule (86,016 B per leaf),
  * per-leaf signal speeds, error flags) for up to p->max_leaves leaves on
  * p->device.  No later call allocates device memory.  *out is NULL on error. */
 int hydro_create(const hydro_params *p, hydro_t **out);
@@ -122,6 +133,30 @@ int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax);
  * out (device [n][7][512][26]); point d = (dx,dy,dz) is numbered
  * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre. */
 int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out);
+
+/* One SSP-RK2 step driven on the device: both stages read dt from dt_dev
+ * (device, one double); afterwards dt_dev holds the next step,
+ * cfl * min over leaves of dx / a_max over both stages.  Never synchronises
+ * and never allocates, so it can be captured into a HIP graph. */
+int hydro_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev);
+
+/* dt_dev = cfl * min over leaves of dx / a_max(g->U): the first step of a run
+ * (signal-speed pre-pass; asynchronous). */
+int hydro_dt(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev);
+
+/* Capture nsteps hydro_step_dev calls on g->stream (must not be NULL) into
+ * a HIP graph held by the handle, replacing any earlier one; the grid's
+ * buffers and launch partition are baked in.  hydro_graph_launch replays it
+ * on `stream`. */
+int hydro_graph_capture(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, int nsteps);
+int hydro_graph_launch(hydro_t *h, void *stream);
+
+/* Time every schedule on stage-1 launches of 1, 2, 4, ... leaves (up to
+ * g->n, each bucket from the first leaves of g) and keep the fastest per
+ * size bucket for HYDRO_SCHED_AUTO; table (host [HYDRO_NBUCKET], may be
+ * NULL) receives it, and cache_path (may be NULL) a JSON copy.  Uses only
+ * the handle's workspace; g->U is read, not written.  Synchronous. */
+int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
 
 /* Device pointer to the per-leaf maximum signal speeds of the last step. */
 const double *hydro_amax_device(const hydro_t *h);

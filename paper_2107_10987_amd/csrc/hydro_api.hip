@@ -8,7 +8,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -19,6 +21,16 @@ struct hydro_t {
     hydro_params p;
     int device;
     double *U1 = nullptr;      // first-stage state [max_leaves][7][512]
+    double *dscr = nullptr;    // column walk: [max_leaves][3][7][512]
+    int *queue = nullptr;      // persistent launches: [2]
+    int *leaf_done = nullptr;  // [max_leaves]
+    double *tile_amax = nullptr;  // [max_leaves][3]
+    int num_cu = 0;
+    int32_t table[HYDRO_NBUCKET];  // schedule per launch-size bucket (HYDRO_SCHED_AUTO)
+    bool table_loaded = false;
+    std::string arch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     double *amax = nullptr;    // per-leaf signal speeds [max_leaves]
     Status *status = nullptr;  // device status word
     hipStream_t last_stream = nullptr;
@@ -99,8 +111,33 @@ int set_device(hydro_t *h) {
 }
 
 // Launch one stage over all leaves, split as the grid asks.
+int bucket_of(int nleaf) {
+    int b = 0;
+    while ((2 << b) <= nleaf && b < HYDRO_NBUCKET - 1) ++b;
+    return b;
+}
+
+// Schedule of a launch of nleaf leaves.
+int resolve_schedule(const hydro_t *h, int nleaf) {
+    if (h->p.schedule != HYDRO_SCHED_AUTO) return h->p.schedule;
+    if (h->table_loaded) return h->table[bucket_of(nleaf)];
+    // built-in rule: spread small launches over (leaf, axis) tiles so they
+    // still occupy most compute units; otherwise a workgroup per leaf
+    return (3 * nleaf <= h->num_cu) ? HYDRO_SCHED_TILED : HYDRO_SCHED_COLUMN;
+}
+
+void set_schedule(StageArgs &a, int sched) {
+    switch (sched) {
+    case HYDRO_SCHED_FACE: a.kernel = KERNEL_FACE; a.tiles = 1; break;
+    case HYDRO_SCHED_PERSISTENT: a.kernel = KERNEL_PERSISTENT; a.tiles = 1; break;
+    case HYDRO_SCHED_TILED: a.kernel = KERNEL_PERSISTENT; a.tiles = 3; break;
+    default: a.kernel = KERNEL_COLUMN; a.tiles = 1; break;
+    }
+}
+
 int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
-              const double *Un, double *Uout, double *amax, int accumulate) {
+              const double *Un, double *Uout, double *amax, int accumulate,
+              const double *dt_dev = nullptr, bool allow_timing = true) {
     StageArgs a;
     a.Uin = Uin;
     a.Un = Un;
@@ -114,6 +151,12 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.dt = dt;
     a.stage = stage;
     a.amax_accumulate = accumulate;
+    a.dscr = h->dscr;
+    a.dt_dev = dt_dev;
+    a.queue = h->queue;
+    a.leaf_done = h->leaf_done;
+    a.tile_amax = h->tile_amax;
+    a.grid_limit = h->num_cu;
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
@@ -121,7 +164,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         a.leaf0 = g->n_launch > 0 ? g->launch_off[b] : 0;
         a.nleaf = g->n_launch > 0 ? g->launch_off[b + 1] - a.leaf0 : g->n;
         if (a.nleaf == 0) continue;
-        const bool rec = h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
+        set_schedule(a, resolve_schedule(h, a.nleaf));
+        const bool rec = allow_timing && h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
         if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], s);
         hipError_t e = hydro_launch_stage(a, s);
         if (e != hipSuccess) return hip_fail(h, e, "stage launch");
@@ -148,6 +192,54 @@ int read_status(hydro_t *h, hipStream_t s) {
     return HYDRO_OK;
 }
 
+// Autotune table as JSON: {"arch": "...", "schedule": [b0, ..., b15]}.
+int load_table(hydro_t *h, const char *path) {
+    std::ifstream f(path);
+    if (!f) return fail(h, HYDRO_EINVAL, std::string("cannot read tune cache ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    const size_t k = t.find("\"schedule\"");
+    const size_t o = k == std::string::npos ? k : t.find('[', k);
+    if (o == std::string::npos) return fail(h, HYDRO_EINVAL, "tune cache has no schedule list");
+    const size_t a = t.find("\"arch\"");
+    if (a != std::string::npos) {
+        const size_t q0 = t.find('"', t.find(':', a) + 1), q1 = t.find('"', q0 + 1);
+        if (q0 != std::string::npos && q1 != std::string::npos && t.substr(q0 + 1, q1 - q0 - 1) != h->arch)
+            return fail(h, HYDRO_EINVAL, "tune cache was made for another GPU");
+    }
+    size_t pos = o + 1;
+    for (int b = 0; b < HYDRO_NBUCKET; ++b) {
+        char *end = nullptr;
+        const long v = strtol(t.c_str() + pos, &end, 10);
+        if (end == t.c_str() + pos || v < HYDRO_SCHED_FACE || v > HYDRO_SCHED_TILED)
+            return fail(h, HYDRO_EINVAL, "bad schedule list in tune cache");
+        h->table[b] = (int32_t)v;
+        pos = (size_t)(end - t.c_str());
+        while (pos < t.size() && (t[pos] == ',' || t[pos] == ' ' || t[pos] == '\n')) ++pos;
+    }
+    h->table_loaded = true;
+    return HYDRO_OK;
+}
+
+int save_table(hydro_t *h, const char *path) {
+    std::ofstream f(path);
+    if (!f) return fail(h, HYDRO_EINVAL, std::string("cannot write tune cache ") + path);
+    f << "{\"arch\": \"" << h->arch << "\", \"schedule\": [";
+    for (int b = 0; b < HYDRO_NBUCKET; ++b) f << (b ? ", " : "") << h->table[b];
+    f << "]}\n";
+    return f.good() ? HYDRO_OK : fail(h, HYDRO_EINVAL, "tune cache write failed");
+}
+
+// Stage 1, stage 2 and the next dt, all on the device.
+int run_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, bool allow_timing) {
+    int rc;
+    if ((rc = run_stage(h, g, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, dt_dev, allow_timing))) return rc;
+    if ((rc = run_stage(h, g, 2, 0.0, h->U1, g->U, g->U, h->amax, 1, dt_dev, allow_timing))) return rc;
+    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -158,6 +250,8 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (!p) return fail(nullptr, HYDRO_EINVAL, "params is NULL");
     if (p->max_leaves <= 0) return fail(nullptr, HYDRO_EINVAL, "max_leaves must be > 0");
     if (p->recon != 0) return fail(nullptr, HYDRO_EINVAL, "recon must be 0 (plain PPM)");
+    if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
+        return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
     hydro_t *h = new (std::nothrow) hydro_t();
     if (!h) return fail(nullptr, HYDRO_ENOMEM, "handle allocation");
@@ -167,9 +261,27 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (rc) { g_create_err = h->err; delete h; return rc; }
     hipError_t e = ensure_ghost_table(h->device);
     if (e != hipSuccess) { rc = hip_fail(h, e, "ghost table upload"); g_create_err = h->err; delete h; return rc; }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, h->device);
+    if (e != hipSuccess) { rc = hip_fail(h, e, "hipGetDeviceProperties"); g_create_err = h->err; delete h; return rc; }
+    h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    h->arch = prop.gcnArchName;
+    for (int b = 0; b < HYDRO_NBUCKET; ++b) h->table[b] = HYDRO_SCHED_COLUMN;
+    if (p->tune_cache && load_table(h, p->tune_cache) != HYDRO_OK) {
+        rc = HYDRO_EINVAL;
+        g_create_err = h->err;
+        delete h;
+        return rc;
+    }
     const size_t n = (size_t)p->max_leaves;
     e = hipMalloc((void **)&h->U1, n * LEAF_STRIDE * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->dscr, n * 3 * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->amax, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->leaf_done, n * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->tile_amax, n * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(h->leaf_done, 0, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->status, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(h->status, 0, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(h->amax, 0, n * sizeof(double));
@@ -191,6 +303,12 @@ int hydro_destroy(hydro_t *h) {
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->U1) (void)hipFree(h->U1);
     if (h->amax) (void)hipFree(h->amax);
+    if (h->dscr) (void)hipFree(h->dscr);
+    if (h->queue) (void)hipFree(h->queue);
+    if (h->leaf_done) (void)hipFree(h->leaf_done);
+    if (h->tile_amax) (void)hipFree(h->tile_amax);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->status) (void)hipFree(h->status);
     delete h;
     return HYDRO_OK;
@@ -242,6 +360,106 @@ int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out) {
     if ((rc = set_device(h))) return rc;
     hipError_t e = hydro_launch_reconstruct(g->U, g->ghost_map, g->n, out, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "reconstruct launch");
+}
+
+int hydro_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !aligned8(g->U) || !dt_dev) return fail(h, HYDRO_EINVAL, "null U or dt_dev");
+    if (!(cfl > 0.0) || !isfinite(cfl)) return fail(h, HYDRO_EINVAL, "cfl must be > 0");
+    if ((rc = set_device(h))) return rc;
+    return run_step_dev(h, g, cfl, dt_dev, true);
+}
+
+int hydro_dt(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !dt_dev) return fail(h, HYDRO_EINVAL, "null U or dt_dev");
+    if (!(cfl > 0.0) || !isfinite(cfl)) return fail(h, HYDRO_EINVAL, "cfl must be > 0");
+    if ((rc = set_device(h))) return rc;
+    if ((rc = run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, h->amax, 0))) return rc;
+    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
+}
+
+int hydro_graph_capture(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, int nsteps) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->stream) return fail(h, HYDRO_EINVAL, "graph capture needs a non-default stream");
+    if (!g->U || !dt_dev || nsteps <= 0) return fail(h, HYDRO_EINVAL, "null U/dt_dev or nsteps <= 0");
+    if (!(cfl > 0.0) || !isfinite(cfl)) return fail(h, HYDRO_EINVAL, "cfl must be > 0");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)g->stream;
+    if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+    if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+    for (int k = 0; k < nsteps && rc == HYDRO_OK; ++k) rc = run_step_dev(h, g, cfl, dt_dev, false);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    h->graph = graph;
+    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+    return HYDRO_OK;
+}
+
+int hydro_graph_launch(hydro_t *h, void *stream) {
+    if (!h) return HYDRO_EINVAL;
+    if (!h->graph_exec) return fail(h, HYDRO_EINVAL, "no graph captured");
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipError_t e = hipGraphLaunch(h->graph_exec, (hipStream_t)stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "hipGraphLaunch");
+}
+
+int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U) return fail(h, HYDRO_EINVAL, "null U");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)g->stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(h, HYDRO_EHIP, "hipEventCreate");
+    const int32_t saved_sched = h->p.schedule;
+    hydro_grid sub = *g;
+    sub.n_launch = 0;
+    sub.launch_off = nullptr;
+    int best_prev = HYDRO_SCHED_COLUMN;
+    for (int b = 0; b < HYDRO_NBUCKET && rc == HYDRO_OK; ++b) {
+        const int size = 1 << b;
+        if (size > g->n) { h->table[b] = best_prev; continue; }
+        sub.n = size;
+        float best_ms = 1e30f;
+        int best = HYDRO_SCHED_COLUMN;
+        for (int sc = HYDRO_SCHED_FACE; sc <= HYDRO_SCHED_TILED && rc == HYDRO_OK; ++sc) {
+            h->p.schedule = sc;
+            const int reps = size >= 256 ? 3 : 10;
+            rc = run_stage(h, &sub, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);   // warm
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == HYDRO_OK; ++r)
+                rc = run_stage(h, &sub, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = hip_fail(h, e, "autotune timing"); break; }
+            if (ms < best_ms) { best_ms = ms; best = sc; }
+        }
+        h->table[b] = best;
+        best_prev = best;
+    }
+    h->p.schedule = saved_sched;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    h->table_loaded = true;
+    if (table) memcpy(table, h->table, sizeof(h->table));
+    if (cache_path) return save_table(h, cache_path);
+    return HYDRO_OK;
 }
 
 const double *hydro_amax_device(const hydro_t *h) { return h ? h->amax : nullptr; }

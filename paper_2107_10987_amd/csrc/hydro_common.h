@@ -49,12 +49,25 @@ struct StageArgs {
     int nleaf;                // leaves in this launch
     int stage;                // 1, 2; 0 = signal speed only
     int amax_accumulate;      // stage 2 of a step: amax = max(amax, this stage)
+    int kernel;               // KERNEL_* below
+    double *dscr;             // column walk: [n][3][7][512] per-axis flux differences
+    const double *dt_dev;     // if set, dt is read from device memory
+    // persistent column walk
+    int tiles;                // 1: whole leaves; 3: one axis per item
+    int grid_limit;           // workgroups of a persistent launch
+    int *queue;               // [2]: next item, workgroups finished (zero between launches)
+    int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
+    double *tile_amax;        // [n][3]
 };
+
+enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
 
 }  // namespace hydro
 
 // Launchers implemented in the kernel translation unit.
 hipError_t hydro_upload_ghost_table(const uint16_t *table);
 hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
+hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
+                           hipStream_t s);
 hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,
                                     hipStream_t s);

@@ -49,9 +49,10 @@ __device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     return (dl * dr > 0.0) ? copysign(m, d) : 0.0;
 }
 
-// PPM on the five values q(c + m*st), m = -2..2, with the CW84 limiter.
-// Returns the value at the +st end when `plus`, else at the -st end.
-__device__ __forceinline__ double ppm_end(const double *q, int c, int st, bool plus) {
+// PPM on the five values q(c + m*st), m = -2..2, with the CW84 limiter:
+// left (-st end) and right (+st end) interface values of the middle cell.
+__device__ __forceinline__ void ppm_both(const double *q, int c, int st, double &left,
+                                         double &right) {
     const double q0 = q[c - 2 * st];
     const double q1 = q[c - st];
     const double q2 = q[c];
@@ -74,6 +75,14 @@ __device__ __forceinline__ double ppm_end(const double *q, int c, int st, bool p
         else if (D * M6 < -(D * D))
             R = 3.0 * q2 - 2.0 * L;
     }
+    left = L;
+    right = R;
+}
+
+// Value at the +st end when `plus`, else at the -st end.
+__device__ __forceinline__ double ppm_end(const double *q, int c, int st, bool plus) {
+    double L, R;
+    ppm_both(q, c, st, L, R);
     return plus ? R : L;
 }
 
@@ -87,7 +96,10 @@ __device__ __forceinline__ void point_state(const double *P, int c, int dx, int 
     int st = dx * SX_ + dy * SY_ + dz * SZ_;
     st = plus ? st : -st;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) U[f] = ppm_end(P + f * NP, c, st, plus);
+    for (int f = 0; f < NF; ++f) {
+        U[f] = ppm_end(P + f * NP, c, st, plus);
+        __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight (register pressure)
+    }
 }
 
 // Euler flux along axis N of one reconstructed state; returns |u_N| + c.
@@ -175,16 +187,16 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Ghost-padded block of one leaf into LDS.
+// Ghost-padded block of one leaf into LDS (nt threads cooperate).
 __device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm,
-                                             int leaf, int tid) {
+                                             int leaf, int tid, int nt) {
     const double *Ul = U + (size_t)leaf * LEAF_STRIDE;
-    for (int e = tid; e < LEAF_STRIDE; e += NT) {
+    for (int e = tid; e < LEAF_STRIDE; e += nt) {
         const int f = e >> 9, c = e & (NC - 1);
         P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = Ul[e];
     }
     const int32_t *g = gm + (size_t)leaf * NG;
-    for (int s = tid; s < NG; s += NT) {
+    for (int s = tid; s < NG; s += nt) {
         const int src = g[s];
         const int p = c_ghost_pad[s];
         if (src >= 0) {
@@ -212,12 +224,75 @@ __device__ __forceinline__ void gather_block(double *P, const double *U, const i
     }
 }
 
+// Flux divergence sum dsum (per field, over the three axes) -> L(U), the
+// rotating-frame source, the stage combine, the tracer resync and the store
+// of one interior cell; non-physical results are reported in a.status.
+__device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c, double dx,
+                                            double dt, const double dsum[NF]) {
+    const double idx = 1.0 / dx;
+    const size_t base = (size_t)leaf * LEAF_STRIDE + c;
+    double u[NF], L[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        L[f] = -dsum[f] * idx;
+        u[f] = a.Uin[base + (size_t)f * NC];
+    }
+    // rotating-frame source -Omega x s
+    L[SX] = L[SX] + a.ph.omega * u[SY];
+    L[SY] = L[SY] - a.ph.omega * u[SX];
+    double o[NF];
+    if (a.stage == 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) o[f] = u[f] + dt * L[f];
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) o[f] = 0.5 * (a.Un[base + (size_t)f * NC] + (u[f] + dt * L[f]));
+        // dual-energy resync of the tracer after the full step
+        const double rinv = 1.0 / o[RHO];
+        const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
+        const double eint = o[EGAS] - ek;
+        if (eint > a.ph.eta2 * o[EGAS]) o[TAU] = pow(eint, 1.0 / a.ph.gamma);
+    }
+    bool bad = !(o[RHO] > 0.0);
+    int badf = bad ? RHO : -1;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        a.Uout[base + (size_t)f * NC] = o[f];
+        if (!isfinite(o[f]) && !bad) {
+            bad = true;
+            badf = f;
+        }
+    }
+    if (bad && atomicCAS(&a.status->flag, 0, 1) == 0) {
+        a.status->leaf = leaf;
+        a.status->cell = c;
+        a.status->field = badf;
+    }
+}
+
+// Time step of this launch: from device memory when the step is driven
+// on the device (graph replay), else the host value.
+__device__ __forceinline__ double stage_dt(const StageArgs &a) {
+    return a.dt_dev ? *a.dt_dev : a.dt;
+}
+
+// Maximum of the per-wave maxima in red[0..nw) -> a.amax[leaf].
+__device__ __forceinline__ void store_amax(const StageArgs &a, int leaf, const double *red, int nw) {
+    double m = red[0];
+    for (int w = 1; w < nw; ++w) m = red[w] > m ? red[w] : m;
+    if (a.amax_accumulate) {
+        const double old = a.amax[leaf];
+        m = old > m ? old : m;
+    }
+    a.amax[leaf] = m;
+}
+
 __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     __shared__ double P[NF * NP];
     const int leaf = a.leaf0 + blockIdx.x;
     const int tid = threadIdx.x;
 
-    gather_block(P, a.Uin, a.gmap, leaf, tid);
+    gather_block(P, a.Uin, a.gmap, leaf, tid, NT);
     __syncthreads();
 
     const double dx = a.dx[leaf];
@@ -249,57 +324,294 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
         const int rx0 = i + 9 * (j + 8 * k), rx1 = rx0 + 1;
         const int ry0 = i + 8 * (j + 9 * k), ry1 = ry0 + 8;
         const int rz0 = i + 8 * (j + 8 * k), rz1 = rz0 + 64;
-        const double idx = 1.0 / dx;
-        const size_t base = (size_t)leaf * LEAF_STRIDE + c;
-        double u[NF], L[NF];
+        double dsum[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const double *Ff = Fl + f * 3 * NT;
-            const double d = (Ff[rx1] - Ff[rx0]) + (Ff[NT + ry1] - Ff[NT + ry0]) +
-                             (Ff[2 * NT + rz1] - Ff[2 * NT + rz0]);
-            L[f] = -d * idx;
-            u[f] = a.Uin[base + (size_t)f * NC];
+            dsum[f] = (Ff[rx1] - Ff[rx0]) + (Ff[NT + ry1] - Ff[NT + ry0]) +
+                      (Ff[2 * NT + rz1] - Ff[2 * NT + rz0]);
         }
-        // rotating-frame source -Omega x s
-        L[SX] = L[SX] + a.ph.omega * u[SY];
-        L[SY] = L[SY] - a.ph.omega * u[SX];
-        double o[NF];
-        if (a.stage == 1) {
+        finish_cell(a, leaf, c, dx, stage_dt(a), dsum);
+    }
+    if (tid == 0 && a.amax) store_amax(a, leaf, red, NT / 64);
+}
+
+
+// ---------------------------------------------------------------------------
+// Column-walk schedule.
+//
+// For axis n, the faces normal to n lie on 64 columns of cells along n.  A
+// column is held by 10 consecutive lanes, one per cell -1..8 along n (six
+// columns per wave, 11 waves per leaf).  For each of the nine lines through
+// a cell that cross a face of axis n (directions e_n + a t1 + b t2), a lane
+// runs PPM once and keeps both ends: the end pointing to -n serves the face
+// below the cell, and the end pointing to +n is passed one lane up to serve
+// the face above it.  The lines are taken in pairs {e_n + a t1 + b t2,
+// e_n - a t1 - b t2}, which are exactly the lines the two points (a,b) and
+// (-a,-b) of a face need.  Each lane then owns the flux of the face below
+// its cell, and one more lane shift gives the flux difference of its cell.
+// A line is reconstructed once per axis it crosses (1.71x the minimal PPM
+// work of a leaf, against 3x for one face per thread).
+// ---------------------------------------------------------------------------
+
+constexpr int NTC = 704;            // 11 waves x 64 lanes
+constexpr int COLS_PER_WAVE = 6;    // 6 columns x 10 cells = 60 lanes
+
+// Both ends of the line through padded cell c along d = (dx,dy,dz) for all
+// fields: pos = value at +d, neg = value at -d (canonical orientation).
+__device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy, int dz,
+                                          double pos[NF], double neg[NF]) {
+    const bool plus = (dx != 0) ? (dx > 0) : ((dy != 0) ? (dy > 0) : (dz > 0));
+    int st = dx * SX_ + dy * SY_ + dz * SZ_;
+    st = plus ? st : -st;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) o[f] = u[f] + a.dt * L[f];
-        } else {
+    for (int f = 0; f < NF; ++f) {
+        double L, R;
+        ppm_both(P + f * NP, c, st, L, R);
+        pos[f] = plus ? R : L;
+        neg[f] = plus ? L : R;
+        // keep the scheduler from hoisting every field's stencil loads at
+        // once: that costs ~70 VGPRs and forces spills at 11 waves per CU
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ double shfl_down1(double v) { return __shfl_down(v, 1, 64); }
+
+// Central-upwind flux at one face point of axis N, Simpson weight w added
+// into acc; returns the signal speed.
+template <int N>
+__device__ __forceinline__ double point_flux_acc(const double UL[NF], const double UR[NF],
+                                                 double xq, double yq, const Phys &ph, double w,
+                                                 double acc[NF]) {
+    double FL[NF], FR[NF];
+    const double sl = side_flux<N>(UL, xq, yq, ph, FL);
+    const double sr = side_flux<N>(UR, xq, yq, ph, FR);
+    const double s = sl > sr ? sl : sr;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) o[f] = 0.5 * (a.Un[base + (size_t)f * NC] + (u[f] + a.dt * L[f]));
-            // dual-energy resync of the tracer after the full step
-            const double rinv = 1.0 / o[RHO];
-            const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
-            const double eint = o[EGAS] - ek;
-            if (eint > a.ph.eta2 * o[EGAS]) o[TAU] = pow(eint, 1.0 / a.ph.gamma);
-        }
-        bool bad = !(o[RHO] > 0.0);
-        int badf = bad ? RHO : -1;
+    for (int f = 0; f < NF; ++f) {
+        const double Fq = 0.5 * (FL[f] + FR[f]) - 0.5 * s * (UR[f] - UL[f]);
+        acc[f] = acc[f] + w * Fq;
+    }
+    return s;
+}
+
+// Flux difference F(face above) - F(face below) along axis N of this lane's
+// cell, for column `col` and cell index `cell` in -1..8.
+template <int N>
+__device__ __forceinline__ void column_axis(const double *P, int col, int cell, double dx,
+                                            double ox, double oy, double oz, const Phys &ph,
+                                            double dsum[NF], double &smax) {
+    const int c1 = col & 7, c2 = col >> 3;
+    // cell B on the walk, in (x, y, z): axis N takes `cell`, t1 < t2 take c1, c2
+    const int bi = (N == 0) ? cell : c1;
+    const int bj = (N == 1) ? cell : ((N == 0) ? c1 : c2);
+    const int bk = (N == 2) ? cell : c2;
+    const int cB = pidx(bi, bj, bk);
+    const double xB = ox + (double)bi * dx;
+    const double yB = oy + (double)bj * dx;
+    (void)oz;
+    const bool face = cell >= 0;     // lanes of cells 0..8 own the face below them
+    double acc[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            a.Uout[base + (size_t)f * NC] = o[f];
-            if (!isfinite(o[f]) && !bad) {
-                bad = true;
-                badf = f;
-            }
-        }
-        if (bad && atomicCAS(&a.status->flag, 0, 1) == 0) {
-            a.status->leaf = leaf;
-            a.status->cell = c;
-            a.status->field = badf;
+    for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+    // direction e_N + a t1 + b t2 in (x, y, z)
+    auto dirx = [](int a, int b) { return (N == 0) ? 1 : a; };
+    auto diry = [](int a, int b) { return (N == 1) ? 1 : ((N == 0) ? a : b); };
+    auto dirz = [](int a, int b) { return (N == 2) ? 1 : b; };
+    // point positions x(B) + d_B dx / 2, d_B = -e_N + a t1 + b t2
+    auto qx = [&](int a, int b) { return xB + 0.5 * (double)((N == 0) ? -1 : a) * dx; };
+    auto qy = [&](int a, int b) { return yB + 0.5 * (double)((N == 1) ? -1 : ((N == 0) ? a : b)) * dx; };
+    {   // the face-normal line serves the face centre
+        double pos[NF], neg[NF], prev[NF];
+        line_ends(P, cB, dirx(0, 0), diry(0, 0), dirz(0, 0), pos, neg);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) prev[f] = shfl_up1(pos[f]);
+        if (face) {
+            const double s = point_flux_acc<N>(prev, neg, qx(0, 0), qy(0, 0), ph, 16.0 / 36.0, acc);
+            smax = s > smax ? s : smax;
         }
     }
-    if (tid == 0 && a.amax) {
-        double m = red[0];
-        for (int w = 1; w < NT / 64; ++w) m = red[w] > m ? red[w] : m;
-        if (a.amax_accumulate) {
-            const double old = a.amax[leaf];
-            m = old > m ? old : m;
+    // line pairs {(a,b), (-a,-b)} for (a,b) = (1,0), (0,1), (1,1), (1,-1)
+#pragma unroll 1
+    for (int p = 0; p < 4; ++p) {
+        const int a = (p == 1) ? 0 : 1;
+        const int b = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
+        const double w = (p < 2) ? 4.0 / 36.0 : 1.0 / 36.0;
+        double pos1[NF], neg1[NF], pos2[NF], neg2[NF];
+        line_ends(P, cB, dirx(a, b), diry(a, b), dirz(a, b), pos1, neg1);
+        line_ends(P, cB, dirx(-a, -b), diry(-a, -b), dirz(-a, -b), pos2, neg2);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            pos1[f] = shfl_up1(pos1[f]);
+            pos2[f] = shfl_up1(pos2[f]);
         }
-        a.amax[leaf] = m;
+        if (face) {
+            // point (a,b): left = +end of line (a,b) below, right = -end of line (-a,-b) here
+            double s = point_flux_acc<N>(pos1, neg2, qx(a, b), qy(a, b), ph, w, acc);
+            smax = s > smax ? s : smax;
+            // point (-a,-b): left = +end of line (-a,-b) below, right = -end of line (a,b) here
+            s = point_flux_acc<N>(pos2, neg1, qx(-a, -b), qy(-a, -b), ph, w, acc);
+            smax = s > smax ? s : smax;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) dsum[f] = shfl_down1(acc[f]) - acc[f];
+}
+
+// Lane geometry of the column walk: column, cell -1..8, and whether the
+// lane holds a real column.
+struct ColLane {
+    int lane, wave, col, cell, c1, c2;
+    bool live;
+    __device__ explicit ColLane(int tid) {
+        lane = tid & 63;
+        wave = tid >> 6;
+        const int slot = lane / 10;
+        col = wave * COLS_PER_WAVE + slot;
+        live = slot < COLS_PER_WAVE && col < NX * NX;
+        col = live ? col : 0;
+        cell = lane - 10 * slot - 1;   // idle lanes reuse a valid cell of column 0
+        c1 = col & 7;
+        c2 = col >> 3;
+    }
+};
+
+// Flux differences of one axis of one leaf into its workspace slice W
+// (linear cell index); returns this lane's signal speed maximum.
+template <int N>
+__device__ __forceinline__ void col_axis_to_ws(const StageArgs &a, const double *P, const ColLane &L,
+                                               int leaf, double *W, double &smax) {
+    const double dx = a.dx[leaf];
+    const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
+    double d[NF];
+    double sm = 0.0;
+    column_axis<N>(P, L.col, L.cell, dx, ox, oy, oz, a.ph, d, sm);
+    smax = L.live && sm > smax ? sm : smax;
+    if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
+        const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
+                    : (N == 1) ? (L.c2 * NX + L.cell) * NX + L.c1
+                               : (L.cell * NX + L.c2) * NX + L.c1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) W[(N * NF + f) * NC + c] = d[f];
+    }
+}
+
+// The final pass of a leaf: sum the three axes' differences from W and
+// finish every interior cell.
+__device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, const double *W,
+                                                int tid, int nt) {
+    if (a.stage == 0) return;
+    const double dx = a.dx[leaf];
+    const double dt = stage_dt(a);
+    for (int c = tid; c < NC; c += nt) {
+        double dsum[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            dsum[f] = (W[(0 * NF + f) * NC + c] + W[(1 * NF + f) * NC + c]) + W[(2 * NF + f) * NC + c];
+        finish_cell(a, leaf, c, dx, dt, dsum);
+    }
+}
+
+// One leaf per workgroup, all three axes.
+__global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
+    __shared__ double P[NF * NP];
+    const int leaf = a.leaf0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    gather_block(P, a.Uin, a.gmap, leaf, tid, NTC);
+    __syncthreads();
+    const ColLane L(tid);
+    double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
+    double smax = 0.0;
+    col_axis_to_ws<0>(a, P, L, leaf, W, smax);
+    col_axis_to_ws<1>(a, P, L, leaf, W, smax);
+    col_axis_to_ws<2>(a, P, L, leaf, W, smax);
+    const double wm = wave_max(smax);
+    __syncthreads();  // the input block is dead; workspace writes are visible
+    double *red = P;
+    if (L.lane == 0) red[L.wave] = wm;
+    __syncthreads();
+    col_finish_leaf(a, leaf, W, tid, NTC);
+    if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
+}
+
+// Persistent workgroups over a queue of (leaf, tile) items.  With one tile a
+// workgroup does whole leaves; with three, an item is one axis of a leaf and
+// the workgroup that completes a leaf's last axis finishes the leaf, so a
+// small batch spreads over three times as many compute units.  The last
+// workgroup to leave resets the queue for the next launch.
+__global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) {
+    __shared__ double P[NF * NP];
+    __shared__ int item_s, last_s;
+    const int tid = threadIdx.x;
+    const ColLane L(tid);
+    const int T = a.tiles;
+    const int items = a.nleaf * T;
+    for (;;) {
+        if (tid == 0) item_s = atomicAdd(&a.queue[0], 1);
+        __syncthreads();
+        const int item = item_s;
+        if (item >= items) break;
+        const int leaf = a.leaf0 + item / T;
+        const int tile = item - (item / T) * T;
+        gather_block(P, a.Uin, a.gmap, leaf, tid, NTC);
+        __syncthreads();
+        double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
+        double smax = 0.0;
+        if (T == 1) {
+            col_axis_to_ws<0>(a, P, L, leaf, W, smax);
+            col_axis_to_ws<1>(a, P, L, leaf, W, smax);
+            col_axis_to_ws<2>(a, P, L, leaf, W, smax);
+        } else if (tile == 0) {
+            col_axis_to_ws<0>(a, P, L, leaf, W, smax);
+        } else if (tile == 1) {
+            col_axis_to_ws<1>(a, P, L, leaf, W, smax);
+        } else {
+            col_axis_to_ws<2>(a, P, L, leaf, W, smax);
+        }
+        const double wm = wave_max(smax);
+        __syncthreads();
+        double *red = P;
+        if (L.lane == 0) red[L.wave] = wm;
+        __syncthreads();
+        if (T == 1) {
+            col_finish_leaf(a, leaf, W, tid, NTC);
+            if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
+        } else {
+            if (tid == 0) {
+                double m = red[0];
+                for (int w = 1; w < NTC / 64; ++w) m = red[w] > m ? red[w] : m;
+                a.tile_amax[(size_t)leaf * 3 + tile] = m;
+                __threadfence();   // publish W and the tile maximum device-wide
+                last_s = atomicAdd(&a.leaf_done[leaf], 1) == T - 1;
+                if (last_s) {
+                    __threadfence();
+                    a.leaf_done[leaf] = 0;
+                }
+            }
+            __syncthreads();
+            if (last_s) {
+                __threadfence();   // see the other tiles' W
+                col_finish_leaf(a, leaf, W, tid, NTC);
+                if (tid == 0 && a.amax) {
+                    double *r = P;   // reuse: the three tile maxima
+                    r[0] = a.tile_amax[(size_t)leaf * 3 + 0];
+                    r[1] = a.tile_amax[(size_t)leaf * 3 + 1];
+                    r[2] = a.tile_amax[(size_t)leaf * 3 + 2];
+                    store_amax(a, leaf, r, 3);
+                }
+            }
+        }
+        __syncthreads();   // LDS and item_s are reused by the next item
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.queue[1], 1) == (int)gridDim.x - 1) {
+            a.queue[0] = 0;
+            a.queue[1] = 0;
+            __threadfence();
+        }
     }
 }
 
@@ -308,7 +620,7 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(const double *U, const 
                                                          double *out) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, threadIdx.x);
+    gather_block(P, U, gm, leaf, threadIdx.x, NT);
     __syncthreads();
     double *o = out + (size_t)leaf * NF * NC * 26;
     for (int e = threadIdx.x; e < NC * 26; e += NT) {
@@ -331,7 +643,48 @@ hipError_t hydro_upload_ghost_table(const uint16_t *table) {
 
 hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
     if (a.nleaf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stage_kernel, dim3(a.nleaf), dim3(NT), 0, s, a);
+    switch (a.kernel) {
+    case KERNEL_FACE:
+        hipLaunchKernelGGL(stage_kernel, dim3(a.nleaf), dim3(NT), 0, s, a);
+        break;
+    case KERNEL_COLUMN:
+        hipLaunchKernelGGL(stage_kernel_col, dim3(a.nleaf), dim3(NTC), 0, s, a);
+        break;
+    default: {   // persistent column walk
+        const int items = a.nleaf * a.tiles;
+        const int grid = items < a.grid_limit ? items : a.grid_limit;
+        hipLaunchKernelGGL(stage_kernel_col_persistent, dim3(grid), dim3(NTC), 0, s, a);
+    }
+    }
+    return hipGetLastError();
+}
+
+// dt_out = cfl * min over leaves of dx / amax (one workgroup).
+__global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double *amax, int n,
+                                                 double cfl, double *dt_out) {
+    __shared__ double red[4];
+    double m = INFINITY;
+    for (int l = threadIdx.x; l < n; l += 256) {
+        const double v = dx[l] / amax[l];
+        m = v < m ? v : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(m, o, 64);
+        m = u < m ? u : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < 4; ++w) r = red[w] < r ? red[w] : r;
+        *dt_out = cfl * r;
+    }
+}
+
+hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, dx, amax, n, cfl, dt_out);
     return hipGetLastError();
 }
 

@@ -18,8 +18,11 @@ OK, EINVAL, ENOMEM, EHIP, ENONPHYS = 0, -1, -2, -3, -4
 NX, NF, NC, NGHOST = 8, 7, 512, 2232
 
 EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_step", "hydro_stage",
-           "hydro_signal_speed", "hydro_reconstruct", "hydro_amax_device", "hydro_check",
-           "hydro_timing", "hydro_strerror", "hydro_last_error")
+           "hydro_signal_speed", "hydro_reconstruct", "hydro_step_dev", "hydro_dt",
+           "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_amax_device",
+           "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error")
+SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
+NBUCKET = 16
 
 
 class HydroError(RuntimeError):
@@ -30,7 +33,8 @@ class HydroError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
-                ("reserved", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double)]
+                ("schedule", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
+                ("tune_cache", C.c_char_p)]
 
 
 class Grid(C.Structure):
@@ -65,6 +69,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_stage.argtypes = [vp, C.POINTER(Grid), C.c_int, C.c_double, vp, vp, vp, vp]
     L.hydro_signal_speed.argtypes = [vp, C.POINTER(Grid), vp]
     L.hydro_reconstruct.argtypes = [vp, C.POINTER(Grid), vp]
+    L.hydro_step_dev.argtypes = [vp, C.POINTER(Grid), C.c_double, vp]
+    L.hydro_dt.argtypes = [vp, C.POINTER(Grid), C.c_double, vp]
+    L.hydro_graph_capture.argtypes = [vp, C.POINTER(Grid), C.c_double, vp, C.c_int]
+    L.hydro_graph_launch.argtypes = [vp, vp]
+    L.hydro_autotune.argtypes = [vp, C.POINTER(Grid), C.c_char_p, C.POINTER(C.c_int32)]
     L.hydro_amax_device.argtypes = [vp]
     L.hydro_amax_device.restype = vp
     L.hydro_check.argtypes = [vp, vp]
@@ -103,12 +112,15 @@ def _ptr(t) -> int:
 class Hydro:
     """A library handle: owns the device workspace for up to ``max_leaves``."""
 
-    def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1):
+    def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
+                 schedule: str = "auto", tune_cache: str | None = None):
         import torch
         self.torch = torch
         self.L = load()
         self.device = device
-        self.p = Params(int(max_leaves), int(device), 0, 0, float(eta1), float(eta2))
+        self.schedule = schedule
+        self.p = Params(int(max_leaves), int(device), 0, SCHEDULES[schedule], float(eta1),
+                        float(eta2), tune_cache.encode() if tune_cache else None)
         h = C.c_void_p()
         rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
         if rc:
@@ -145,6 +157,28 @@ class Hydro:
     def stage(self, g: "DeviceGrid", stage: int, dt: float, Uin, Un, Uout, amax=None):
         self._check(self.L.hydro_stage(self.h, C.byref(g.c), int(stage), float(dt), _ptr(Uin),
                                        _ptr(Un), _ptr(Uout), _ptr(amax)))
+
+    def step_dev(self, g: "DeviceGrid", cfl: float, dt_dev):
+        """Step with dt read from / the next dt written to device dt_dev."""
+        self._check(self.L.hydro_step_dev(self.h, C.byref(g.c), float(cfl), _ptr(dt_dev)))
+
+    def dt(self, g: "DeviceGrid", cfl: float, dt_dev):
+        self._check(self.L.hydro_dt(self.h, C.byref(g.c), float(cfl), _ptr(dt_dev)))
+
+    def graph_capture(self, g: "DeviceGrid", cfl: float, dt_dev, nsteps: int):
+        self._check(self.L.hydro_graph_capture(self.h, C.byref(g.c), float(cfl), _ptr(dt_dev),
+                                               int(nsteps)))
+
+    def graph_launch(self, stream=None):
+        s = None if stream is None else int(stream.cuda_stream) or None
+        self._check(self.L.hydro_graph_launch(self.h, s))
+
+    def autotune(self, g: "DeviceGrid", cache_path: str | None = None):
+        table = (C.c_int32 * NBUCKET)()
+        self._check(self.L.hydro_autotune(self.h, C.byref(g.c),
+                                          cache_path.encode() if cache_path else None, table))
+        inv = {v: k for k, v in SCHEDULES.items()}
+        return [inv[v] for v in table]
 
     def signal_speed(self, g: "DeviceGrid"):
         a = self.torch.empty(g.n, dtype=self.torch.float64, device=g.U.device)
