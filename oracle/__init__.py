@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hydro_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "mlp_oracle.c")]
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libhydro_oracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-lm"]
@@ -26,9 +27,10 @@ NF, NC = 7, 512
 def build(force: bool = True) -> str:
     """Compile the oracle library with gcc (contraction off, IEEE FP64)."""
     os.makedirs(BUILD, exist_ok=True)
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    newest = max(os.path.getmtime(f) for f in SRCS + [os.path.join(HERE, "hydro_oracle.h")])
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS[:-3], "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS[:-3], "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -64,6 +66,20 @@ def lib():
         L.oracle_signal_speed.argtypes = [C.c_void_p, dp, dp, dp, C.POINTER(Phys),
                                           C.c_int, C.c_int, dp]
         L.oracle_reconstruct.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
+        fp = C.POINTER(C.c_float)
+        L.oracle_bf16.argtypes = [C.c_double]
+        L.oracle_bf16.restype = C.c_double
+        L.oracle_mlp_forward.argtypes = [fp, C.c_int, dp, C.c_int, dp, dp, dp, dp, dp]
+        L.oracle_mlp_loss_grad.argtypes = [fp, C.c_int, dp, dp, C.c_int, dp]
+        L.oracle_mlp_loss_grad.restype = C.c_double
+        L.oracle_adam.argtypes = [fp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_int]
+        L.oracle_mlp_features.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp]
+        L.oracle_mlp_row_ok.argtypes = [dp, dp, C.c_int]
+        L.oracle_learned_values.argtypes = [dp, fp, dp, ip, ip]
+        L.oracle_reconstruct_values.argtypes = [dp, dp]
+        L.oracle_stage_learned.argtypes = [C.c_void_p, fp, C.c_int, C.c_double, dp, dp, dp, dp,
+                                           C.POINTER(Phys), C.c_int, C.c_int, dp, dp, ip]
         _lib = L
     return _lib
 
@@ -180,6 +196,30 @@ class Oracle:
         l1 = self.n if l1 is None else l1
         return amax[l0:l1]
 
+    def stage_learned(self, params, stage: int, dt: float, Uin, Un=None, l0=0, l1=None):
+        """One stage with the learned reconstruction (plain-PPM fallback per
+        cell); returns (Uout, amax, fallback cells per leaf) for [l0, l1)."""
+        par = np.ascontiguousarray(params, dtype=np.float32)
+        Uin = _f64(Uin)
+        Un = Uin if Un is None else _f64(Un)
+        Uout = np.zeros_like(Uin)
+        amax = np.zeros(self.n)
+        fb = np.zeros(self.n, dtype=np.int32)
+        L = lib()
+
+        def fn(a, b):
+            return L.oracle_stage_learned(self._t, _p(par, C.c_float), stage, float(dt), _p(Uin),
+                                          _p(Un), _p(self.dx), _p(self.origin), C.byref(self.phys),
+                                          a, b, _p(Uout), _p(amax), _p(fb, C.c_int))
+        self._run(fn, self._ranges(l0, l1))
+        l1 = self.n if l1 is None else l1
+        return Uout[l0:l1], amax[l0:l1], fb[l0:l1]
+
+    def step_learned(self, params, dt: float, U):
+        U1, a1, f1 = self.stage_learned(params, 1, dt, U)
+        U2, a2, f2 = self.stage_learned(params, 2, dt, U1, U)
+        return U2, np.maximum(a1, a2), f1 + f2
+
     def dt(self, U, cfl=0.4):
         a = self.signal_speed(U)
         return float(cfl * np.min(self.dx / a))
@@ -230,3 +270,68 @@ def leaf_fluxes(P, dx, origin, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
 def dir26(d) -> int:
     k = 9 * (d[2] + 1) + 3 * (d[1] + 1) + (d[0] + 1)
     return k if k < 13 else k - 1
+
+
+# ---------------------------------------------------------------------------
+# learned reconstruction (MLP) oracle
+# ---------------------------------------------------------------------------
+MLP_NPARAM = 8090
+MLP_SLICES = {"W1": (0, (64, 34)), "b1": (2176, (64,)), "W2": (2240, (64, 64)), "b2": (6336, (64,)),
+              "W3": (6400, (26, 64)), "b3": (8064, (26,))}
+
+
+def bf16(v: float) -> float:
+    return lib().oracle_bf16(float(v))
+
+
+def mlp_forward(params, x, emulate=True):
+    par = np.ascontiguousarray(params, dtype=np.float32)
+    x = _f64(x)
+    B = x.shape[0]
+    y = np.zeros((B, 26))
+    lib().oracle_mlp_forward(_p(par, C.c_float), int(emulate), _p(x), B, _p(y), None, None, None, None)
+    return y
+
+
+def mlp_loss_grad(params, x, t, emulate=True):
+    par = np.ascontiguousarray(params, dtype=np.float32)
+    x, t = _f64(x), _f64(t)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().oracle_mlp_loss_grad(_p(par, C.c_float), int(emulate), _p(x), _p(t), x.shape[0], _p(g))
+    return loss, g
+
+
+def adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float32 params and float64 moments."""
+    n = params.size
+    lib().oracle_adam(_p(params, C.c_float), _p(_f64(grad)), _p(m), _p(v), int(t), lr, b1, b2, eps, n)
+
+
+def mlp_features(P, i, j, k, f):
+    """(nb[27], sigma, x[34] or None if flat) of field f at cell (i,j,k)."""
+    P = _f64(P)
+    nb, s, x = np.zeros(27), C.c_double(), np.zeros(34)
+    flat = lib().oracle_mlp_features(_p(P), i, j, k, f, _p(nb), C.byref(s), _p(x))
+    return nb, s.value, (None if flat else x)
+
+
+def mlp_row_ok(nb, vals, f) -> bool:
+    return bool(lib().oracle_mlp_row_ok(_p(_f64(nb)), _p(_f64(vals)), int(f)))
+
+
+def learned_values(P, params):
+    """Learned point-value table [1000][26][7] of one padded block, with the
+    count of needed cells and of those that fell back to plain PPM."""
+    P = _f64(P)
+    par = np.ascontiguousarray(params, dtype=np.float32)
+    V = np.zeros((1000, 26, NF))
+    nn, nf = C.c_int(), C.c_int()
+    lib().oracle_learned_values(_p(P), _p(par, C.c_float), _p(V), C.byref(nn), C.byref(nf))
+    return V, nn.value, nf.value
+
+
+def reconstruct_values(P):
+    P = _f64(P)
+    V = np.zeros((1000, 26, NF))
+    lib().oracle_reconstruct_values(_p(P), _p(V))
+    return V

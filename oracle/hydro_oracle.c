@@ -301,6 +301,8 @@ static void reconstruct_block(const double *P, double *V)
                 }
 }
 
+void oracle_reconstruct_values(const double *P, double *V) { reconstruct_block(P, V); }
+
 void oracle_leaf_reconstruct(const double *P, double *out)
 {
     double *V = (double *)malloc(sizeof(double) * RB * RB * RB * 26 * NFLD);
@@ -322,6 +324,14 @@ double oracle_leaf_fluxes(const double *P, double dx, const double origin[3], co
 {
     double *V = (double *)malloc(sizeof(double) * RB * RB * RB * 26 * NFLD);
     reconstruct_block(P, V);
+    double smax = oracle_leaf_fluxes_from_values(V, dx, origin, ph, Fn);
+    free(V);
+    return smax;
+}
+
+double oracle_leaf_fluxes_from_values(const double *V, double dx, const double origin[3],
+                                      const oracle_phys *ph, double *Fn)
+{
     double smax = 0.0;
     for (int n = 0; n < 3; ++n) {
         int t1 = (n == 0) ? 1 : 0;
@@ -359,15 +369,23 @@ double oracle_leaf_fluxes(const double *P, double dx, const double origin[3], co
                     for (int f = 0; f < NFLD; ++f) dst[f] = acc[f];
                 }
     }
-    free(V);
     return smax;
 }
 
 void oracle_leaf_rhs(const double *P, double dx, const double origin[3], const oracle_phys *ph,
                      double *dU, double *amax)
 {
+    double *V = (double *)malloc(sizeof(double) * RB * RB * RB * 26 * NFLD);
+    reconstruct_block(P, V);
+    oracle_leaf_rhs_from_values(V, P, dx, origin, ph, dU, amax);
+    free(V);
+}
+
+void oracle_leaf_rhs_from_values(const double *V, const double *P, double dx, const double origin[3],
+                                 const oracle_phys *ph, double *dU, double *amax)
+{
     double *Fn = (double *)malloc(sizeof(double) * 3 * 9 * NX * NX * NFLD);
-    double smax = oracle_leaf_fluxes(P, dx, origin, ph, Fn);
+    double smax = oracle_leaf_fluxes_from_values(V, dx, origin, ph, Fn);
     /* flux divergence plus the rotating-frame source (Omega sy, -Omega sx) */
     double idx = 1.0 / dx;
 #define FX(i, j, k, f) Fn[((((long)0 * 9 + (i)) * NX + (j)) * NX + (k)) * NFLD + (f)]

@@ -49,6 +49,18 @@ int oracle_fill_padded(const void *t, const double *U, int l0, int l1, double *P
  * block: out[7][512][26]. */
 void oracle_leaf_reconstruct(const double *P, double *out);
 
+/* Reconstructed values of the cells -1..8 per axis of one padded block:
+ * V[(k+1)*100 + (j+1)*10 + (i+1)][dir26][7]. */
+void oracle_reconstruct_values(const double *P, double *V);
+
+/* Face fluxes and L(U) from a table of point values laid out as above (the
+ * plain reconstruction or a learned one); P supplies the cell values used by
+ * the source term. */
+double oracle_leaf_fluxes_from_values(const double *V, double dx, const double origin[3],
+                                      const oracle_phys *ph, double *Fn);
+void oracle_leaf_rhs_from_values(const double *V, const double *P, double dx, const double origin[3],
+                                 const oracle_phys *ph, double *dU, double *amax);
+
 /* Face fluxes of one leaf: Fn[3][9][8][8][7] (axis, face along the axis, the
  * other two axes in increasing order, field); returns the max signal speed. */
 double oracle_leaf_fluxes(const double *P, double dx, const double origin[3], const oracle_phys *ph,

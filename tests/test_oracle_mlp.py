@@ -1,0 +1,137 @@
+"""Pins of the learned-reconstruction oracle.
+
+bfloat16 rounding against hand-computed ties; tanh-GELU at a closed-form
+point; the FP64 backward pass against central finite differences; a flat
+neighbourhood passes through exactly; an output bias far outside the
+neighbour bounds sends every cell to plain PPM, and the learned step is then
+bit-for-bit the plain step; the learned step conserves on a periodic leaf;
+and the plain PPM values themselves pass the acceptance test."""
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd.workloads import blast_single_leaf, sedov_uniform
+
+
+def _params(seed=0, scale=0.2):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=8090) * scale).astype(np.float32)
+
+
+def test_bf16_round_to_nearest_even(oracle_mod):
+    bf = oracle_mod.bf16
+    assert bf(1.0) == 1.0
+    assert bf(1 + 2 ** -8) == 1.0                  # tie -> even (1.0)
+    assert bf(1 + 3 * 2 ** -8) == 1 + 2 ** -6      # tie -> even (1 + 2^-6)
+    assert bf(1 + 2 ** -8 + 2 ** -20) == 1 + 2 ** -7
+    assert bf(-2.5) == -2.5
+    assert bf(3.0e38) == float(np.float32(3.0e38)) or bf(3.0e38) > 3e38
+
+
+def test_forward_matches_numpy_in_fp64_mode(oracle_mod):
+    # a plain numpy rendering of the 34-64-64-26 network with tanh-GELU
+    p = _params(1).astype(np.float64)
+    W1, b1 = p[:2176].reshape(64, 34), p[2176:2240]
+    W2, b2 = p[2240:6336].reshape(64, 64), p[6336:6400]
+    W3, b3 = p[6400:8064].reshape(26, 64), p[8064:]
+    c = np.sqrt(2 / np.pi)
+    gelu = lambda z: 0.5 * z * (1 + np.tanh(c * (z + 0.044715 * z ** 3)))   # noqa: E731
+    x = np.random.default_rng(2).normal(size=(8, 34))
+    y = gelu(gelu(x @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+    got = oracle_mod.mlp_forward(_params(1), x, emulate=False)
+    assert np.allclose(got, y, rtol=1e-12, atol=1e-12)
+    assert abs(gelu(np.array(1.0)) - 0.8411919906082768) < 1e-15
+
+
+def test_backward_matches_finite_differences(oracle_mod):
+    rng = np.random.default_rng(3)
+    p = _params(4)
+    x = rng.normal(size=(16, 34))
+    t = rng.normal(size=(16, 26))
+    _, g = oracle_mod.mlp_loss_grad(p, x, t, emulate=False)
+    idx = np.concatenate([rng.choice(8064, 150, replace=False), np.arange(8064, 8090)])
+    h = np.float32(2.0 ** -12)
+    fd = []
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] = p[i] + h
+        pm[i] = p[i] - h
+        lp, _ = oracle_mod.mlp_loss_grad(pp, x, t, emulate=False)
+        lm, _ = oracle_mod.mlp_loss_grad(pm, x, t, emulate=False)
+        fd.append((lp - lm) / (float(pp[i]) - float(pm[i])))
+    fd = np.array(fd)
+    assert np.linalg.norm(fd - g[idx]) <= 1e-6 * np.linalg.norm(g[idx])
+
+
+def test_emulated_backward_close_to_fp64(oracle_mod):
+    rng = np.random.default_rng(5)
+    p = _params(6)
+    x = rng.normal(size=(64, 34))
+    t = rng.normal(size=(64, 26))
+    _, g64 = oracle_mod.mlp_loss_grad(p, x, t, emulate=False)
+    _, g16 = oracle_mod.mlp_loss_grad(p, x, t, emulate=True)
+    # bfloat16 operands (8 significant bits) move the gradient by ~1 %
+    assert np.linalg.norm(g16 - g64) <= 0.05 * np.linalg.norm(g64)
+
+
+def test_adam_first_step_moves_by_lr(oracle_mod):
+    p = np.ones(10, dtype=np.float32)
+    g = np.linspace(-1, 1, 10) + 0.05
+    m, v = np.zeros(10), np.zeros(10)
+    oracle_mod.adam(p, g, m, v, 1, lr=1e-3)
+    # the first bias-corrected Adam step is lr * sign(g) (up to eps)
+    assert np.allclose(p, 1.0 - 1e-3 * np.sign(g), atol=1e-6)
+
+
+def _block_of(w, U=None, leaf=0):
+    import oracle
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    return o.padded(w.U if U is None else U, leaf, leaf + 1)[0]
+
+
+def test_flat_neighbourhood_passes_through(oracle_mod):
+    w = sedov_uniform(4)
+    P = _block_of(w, leaf=0)          # a corner leaf far from the blast: uniform
+    V, needed, fb = oracle_mod.learned_values(P, _params(7))
+    assert needed == 896 and fb == 0
+    for f in range(7):
+        assert np.all(V[:, :, f] == P[f, 3, 3, 3])
+
+
+def test_plain_ppm_values_pass_the_check(oracle_mod):
+    w = blast_single_leaf()
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    P = o.padded(U)[0]
+    V = oracle_mod.reconstruct_values(P)
+    fails = 0
+    for (i, j, k) in [(2, 3, 4), (3, 3, 3), (4, 5, 2), (0, 0, 0), (7, 4, 4)]:
+        c = (k + 1) * 100 + (j + 1) * 10 + (i + 1)
+        for f in range(7):
+            nb, s, x = oracle_mod.mlp_features(P, i, j, k, f)
+            fails += not oracle_mod.mlp_row_ok(nb, V[c, :, f], f)
+    # PPM values lie between neighbours and satisfy the monotonicity
+    # conditions (corrected pairs sit on the boundary, within the slack)
+    assert fails == 0
+
+
+def test_adversarial_bias_falls_back_everywhere_bitwise(oracle_mod):
+    w = blast_single_leaf()
+    p = _params(8)
+    p[8064:] = 10.0                   # every output ten sigmas out of bounds
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    dt = o.dt(w.U)
+    Up, ap = o.step(dt, w.U)
+    Ul, al, fb = o.step_learned(p, dt, w.U)
+    assert fb.sum() > 0
+    assert np.array_equal(Up, Ul) and np.array_equal(ap, al)
+
+
+def test_learned_step_conserves(oracle_mod):
+    w = blast_single_leaf()
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    dt = o.dt(w.U)
+    U1, _, fb = o.step_learned(_params(9, 0.05), dt, w.U)
+    for f in (0, 4, 6):
+        assert abs(U1[:, f].sum() - w.U[:, f].sum()) <= 1e-14 * np.abs(w.U[:, f]).sum()
+    for f in (1, 2, 3):
+        assert abs(U1[:, f].sum()) <= 1e-14 * max(np.abs(U1[:, f]).sum(), 1e-300)
