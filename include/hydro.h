@@ -60,12 +60,15 @@ typedef struct hydro_t hydro_t;
 typedef struct hydro_params {
     int32_t max_leaves; /* capacity of every workspace, in leaves (> 0)             */
     int32_t device;     /* HIP device ordinal                                        */
-    int32_t recon;      /* 0: plain PPM reconstruction                               */
+    int32_t recon;      /* 0: plain PPM; 1: learned reconstruction with FP64 check and
+                           plain-PPM fallback per cell (hydro_mlp_load first)       */
     int32_t schedule;   /* HYDRO_SCHED_*                                             */
     double eta1;        /* dual energy: e < eta1*E at a point -> e = tau^gamma (1e-3) */
     double eta2;        /* dual energy: e > eta2*E after a step -> tau = e^(1/gamma)  */
     const char *tune_cache; /* NULL, or a JSON table written by hydro_autotune: loaded
                                at creation and used by HYDRO_SCHED_AUTO            */
+    int32_t mlp_batch;  /* rows of the network's training workspace (0: 4096)     */
+    int32_t reserved;
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */
@@ -157,6 +160,43 @@ int hydro_graph_launch(hydro_t *h, void *stream);
  * NULL) receives it, and cache_path (may be NULL) a JSON copy.  Uses only
  * the handle's workspace; g->U is read, not written.  Synchronous. */
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
+
+/* ---- learned reconstruction ----------------------------------------------
+ * A 34-64-64-26 network (tanh-GELU) maps the normalised 3x3x3 neighbourhood of
+ * a cell, x_k = (q_nb - q_c)/sigma with sigma = max |q_nb - q_c|, plus a
+ * one-hot field id, to the 26 point values q_c + sigma*y_d.  It runs on
+ * bfloat16 MFMA with FP32 accumulation; every value is checked in FP64
+ * (between the cell and its neighbour in that direction, PPM monotonicity of
+ * each line's pair, rho, E, tau > 0 and X >= 0) and a cell any of whose
+ * fields fails takes plain PPM.  Fluxes, update and conservation stay FP64.
+ * Parameters: float32 vector of 8090 values, W1[64][34], b1[64], W2[64][64],
+ * b2[64], W3[26][64], b3[26].  Not a method of the paper: an extension. */
+
+/* Set the network's parameters (host [8090]); resets the Adam state.
+ * Synchronous. */
+int hydro_mlp_load(hydro_t *h, const float *params);
+/* Copy the current float32 parameters to host params[8090]. Synchronous. */
+int hydro_mlp_save(hydro_t *h, float *params);
+/* Network outputs Y (device [B][26]) for inputs X (device [B][34]),
+ * B <= mlp_batch.  Asynchronous on stream. */
+int hydro_mlp_forward(hydro_t *h, const float *X, int B, float *Y, void *stream);
+/* Gradient of the mean-square loss over B rows and 26 outputs against
+ * targets T (device [B][26]) into grad (device [8090]); loss (device, one
+ * float, may be NULL).  Deterministic.  Asynchronous on stream. */
+int hydro_mlp_grad(hydro_t *h, const float *X, const float *T, int B, float *grad, float *loss,
+                   void *stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr on a batch;
+ * loss as in hydro_mlp_grad.  Asynchronous on stream. */
+int hydro_mlp_train_step(hydro_t *h, const float *X, const float *T, int B, double lr, float *loss,
+                         void *stream);
+/* Training pairs from the plain reconstruction of g->U: rows
+ * [leaf][cell][field] of the interior cells, X (device [n*3584][34]), the
+ * plain PPM point values in the same normalisation T (device [n*3584][26]),
+ * valid (device [n*3584], 0 where the neighbourhood is flat). */
+int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t *valid);
+/* Cells reconstructed by the learned path and cells that fell back to plain
+ * PPM since the previous call (synchronises). */
+int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback);
 
 /* Device pointer to the per-leaf maximum signal speeds of the last step. */
 const double *hydro_amax_device(const hydro_t *h);

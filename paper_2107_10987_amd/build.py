@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libhydro.so")
 ARCH = "gfx950"
 
-SOURCES = ["stage_kernel.hip", "hydro_api.hip"]
+SOURCES = ["stage_kernel.hip", "mlp_kernels.hip", "hydro_api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",
@@ -25,6 +25,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-ffp-contract=off",
+    "-fno-strict-aliasing",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",

@@ -2,6 +2,7 @@
 // management, argument validation, stage sequencing and the octree ghost map.
 
 #include "hydro_common.h"
+#include "mlp_common.h"
 #include "../../include/hydro.h"
 
 #include <math.h>
@@ -31,6 +32,18 @@ struct hydro_t {
     std::string arch;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // learned reconstruction
+    mlp::MlpTrain mt{};
+    int mlp_batch = 0;
+    int adam_t = 0;
+    bool mlp_loaded = false;
+    float *mlp_y = nullptr;        // [max_leaves][896][7][26]
+    double *mlp_sigma = nullptr;   // [max_leaves][896][7]
+    uint8_t *mlp_ok = nullptr;     // [max_leaves][896]
+    uint16_t *ghost_pad = nullptr; // [2232]
+    unsigned long long *fb_count = nullptr;
+    int64_t mlp_cells = 0;
+    std::vector<void *> mlp_bufs;  // everything allocated for the network
     double *amax = nullptr;    // per-leaf signal speeds [max_leaves]
     Status *status = nullptr;  // device status word
     hipStream_t last_stream = nullptr;
@@ -69,6 +82,20 @@ std::vector<uint16_t> ghost_table() {
     return t;
 }
 
+// 12^3 index (cells -2..9 per axis) of each needed cell slot of the
+// learned reconstruction.
+std::vector<uint16_t> slot_table() {
+    std::vector<uint16_t> t(mlp::NSLOT, 0);
+    for (int k = -1; k <= NX; ++k)
+        for (int j = -1; j <= NX; ++j)
+            for (int i = -1; i <= NX; ++i) {
+                const int out = (i < 0 || i >= NX) + (j < 0 || j >= NX) + (k < 0 || k >= NX);
+                if (out > 1) continue;
+                t[mlp::slot_of(i, j, k)] = (uint16_t)(((k + 2) * 12 + (j + 2)) * 12 + (i + 2));
+            }
+    return t;
+}
+
 std::once_flag g_table_once[64];
 hipError_t g_table_err[64];
 
@@ -77,6 +104,10 @@ hipError_t ensure_ghost_table(int dev) {
     std::call_once(g_table_once[dev], [dev] {
         std::vector<uint16_t> t = ghost_table();
         g_table_err[dev] = hydro_upload_ghost_table(t.data());
+        if (g_table_err[dev] == hipSuccess) {
+            std::vector<uint16_t> st = slot_table();
+            g_table_err[dev] = hydro_mlp_upload_slots(st.data());
+        }
     });
     return g_table_err[dev];
 }
@@ -138,6 +169,8 @@ void set_schedule(StageArgs &a, int sched) {
 int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
               const double *Un, double *Uout, double *amax, int accumulate,
               const double *dt_dev = nullptr, bool allow_timing = true) {
+    if (h->p.recon == 1 && !h->mlp_loaded)
+        return fail(h, HYDRO_EINVAL, "learned reconstruction needs hydro_mlp_load first");
     StageArgs a;
     a.Uin = Uin;
     a.Un = Un;
@@ -157,6 +190,9 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.leaf_done = h->leaf_done;
     a.tile_amax = h->tile_amax;
     a.grid_limit = h->num_cu;
+    a.mlp_y = nullptr;
+    a.mlp_sigma = nullptr;
+    a.mlp_ok = nullptr;
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
@@ -165,6 +201,27 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         a.nleaf = g->n_launch > 0 ? g->launch_off[b + 1] - a.leaf0 : g->n;
         if (a.nleaf == 0) continue;
         set_schedule(a, resolve_schedule(h, a.nleaf));
+        if (h->p.recon == 1) {
+            // the network's point values and per-cell verdicts for this launch
+            mlp::MlpInfer m;
+            m.U = Uin;
+            m.gmap = g->ghost_map;
+            m.ghost_pad = h->ghost_pad;
+            m.wb = h->mt.wb;
+            m.par = h->mt.par;
+            m.y = h->mlp_y;
+            m.sigma = h->mlp_sigma;
+            m.cell_ok = h->mlp_ok;
+            m.fb_count = h->fb_count;
+            m.leaf0 = a.leaf0;
+            hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, s);
+            if (e != hipSuccess) return hip_fail(h, e, "inference launch");
+            h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
+            a.mlp_y = h->mlp_y;
+            a.mlp_sigma = h->mlp_sigma;
+            a.mlp_ok = h->mlp_ok;
+            if (a.kernel == KERNEL_FACE) a.kernel = KERNEL_COLUMN;   // the face walk has no learned variant
+        }
         const bool rec = allow_timing && h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
         if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], s);
         hipError_t e = hydro_launch_stage(a, s);
@@ -240,6 +297,61 @@ int run_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, bo
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
 }
 
+template <class T>
+hipError_t mlp_alloc(hydro_t *h, T **p, size_t count) {
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e == hipSuccess) {
+        h->mlp_bufs.push_back((void *)*p);
+        e = hipMemset((void *)*p, 0, count * sizeof(T));
+    }
+    return e;
+}
+
+// Network parameters, Adam state and training workspace (always: a few MB),
+// plus the per-leaf inference outputs when the learned path is on.
+hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
+    const size_t B = h->p.mlp_batch > 0 ? (size_t)h->p.mlp_batch : 4096;
+    h->mlp_batch = (int)B;
+    mlp::MlpTrain &t = h->mt;
+    hipError_t e = mlp_alloc(h, &t.par, mlp::NPAR);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.m, mlp::NPAR);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.v, mlp::NPAR);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.grad, mlp::NPAR);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.wb, mlp::WB_SIZE);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.wbT, mlp::WBT_SIZE);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.xb, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.a1, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.a2, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.dz1, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.dz2, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.z1, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.z2, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.dz1f, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.dz2f, B * 64);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.y, B * 32);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.dy, B * 32);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.loss_rows, B);
+    if (e == hipSuccess) e = mlp_alloc(h, &h->fb_count, 1);
+    if (e == hipSuccess && h->p.recon == 1) {
+        e = mlp_alloc(h, &h->mlp_y, nleaves * mlp::NSLOT * NF * 26);
+        if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_sigma, nleaves * mlp::NSLOT * NF);
+        if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_ok, nleaves * mlp::NSLOT);
+        if (e == hipSuccess) e = mlp_alloc(h, &h->ghost_pad, (size_t)NG);
+        if (e == hipSuccess) {
+            std::vector<uint16_t> gt = ghost_table();
+            e = hipMemcpy(h->ghost_pad, gt.data(), sizeof(uint16_t) * NG, hipMemcpyHostToDevice);
+        }
+    }
+    return e;
+}
+
+int check_batch(hydro_t *h, const void *X, int B) {
+    if (!X) return fail(h, HYDRO_EINVAL, "null network input");
+    if (B <= 0 || B > h->mlp_batch)
+        return fail(h, HYDRO_EINVAL, "batch must be in 1.." + std::to_string(h->mlp_batch));
+    return HYDRO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -249,7 +361,8 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     *out = nullptr;
     if (!p) return fail(nullptr, HYDRO_EINVAL, "params is NULL");
     if (p->max_leaves <= 0) return fail(nullptr, HYDRO_EINVAL, "max_leaves must be > 0");
-    if (p->recon != 0) return fail(nullptr, HYDRO_EINVAL, "recon must be 0 (plain PPM)");
+    if (p->recon != 0 && p->recon != 1) return fail(nullptr, HYDRO_EINVAL, "recon must be 0 or 1");
+    if (p->mlp_batch < 0) return fail(nullptr, HYDRO_EINVAL, "mlp_batch must be >= 0");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
         return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
@@ -280,6 +393,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->leaf_done, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->tile_amax, n * 3 * sizeof(double));
+    if (e == hipSuccess) e = alloc_mlp(h, n);
     if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMemset(h->leaf_done, 0, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->status, sizeof(Status));
@@ -307,6 +421,7 @@ int hydro_destroy(hydro_t *h) {
     if (h->queue) (void)hipFree(h->queue);
     if (h->leaf_done) (void)hipFree(h->leaf_done);
     if (h->tile_amax) (void)hipFree(h->tile_amax);
+    for (void *b : h->mlp_bufs) (void)hipFree(b);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->status) (void)hipFree(h->status);
@@ -459,6 +574,109 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
     h->table_loaded = true;
     if (table) memcpy(table, h->table, sizeof(h->table));
     if (cache_path) return save_table(h, cache_path);
+    return HYDRO_OK;
+}
+
+int hydro_mlp_load(hydro_t *h, const float *params) {
+    if (!h) return HYDRO_EINVAL;
+    if (!params) return fail(h, HYDRO_EINVAL, "null params");
+    int rc = set_device(h);
+    if (rc) return rc;
+    for (int i = 0; i < mlp::NPAR; ++i)
+        if (!isfinite(params[i])) return fail(h, HYDRO_EINVAL, "non-finite parameter");
+    hipError_t e = hipMemcpy(h->mt.par, params, sizeof(float) * mlp::NPAR, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(h->mt.m, 0, sizeof(float) * mlp::NPAR);
+    if (e == hipSuccess) e = hipMemset(h->mt.v, 0, sizeof(float) * mlp::NPAR);
+    if (e == hipSuccess) e = hydro_mlp_launch_pack(h->mt, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(h, e, "network load");
+    h->adam_t = 0;
+    h->mlp_loaded = true;
+    return HYDRO_OK;
+}
+
+int hydro_mlp_save(hydro_t *h, float *params) {
+    if (!h) return HYDRO_EINVAL;
+    if (!params) return fail(h, HYDRO_EINVAL, "null params");
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(params, h->mt.par, sizeof(float) * mlp::NPAR, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "network save");
+}
+
+int hydro_mlp_forward(hydro_t *h, const float *X, int B, float *Y, void *stream) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = check_batch(h, X, B);
+    if (rc) return rc;
+    if (!Y) return fail(h, HYDRO_EINVAL, "null output");
+    if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hydro_mlp_launch_forward(h->mt, X, B, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(Y, 26 * sizeof(float), h->mt.y, 32 * sizeof(float), 26 * sizeof(float), B,
+                             hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "network forward");
+}
+
+int hydro_mlp_grad(hydro_t *h, const float *X, const float *T, int B, float *grad, float *loss,
+                   void *stream) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = check_batch(h, X, B);
+    if (rc) return rc;
+    if (!T || !grad) return fail(h, HYDRO_EINVAL, "null targets or gradient");
+    if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hydro_mlp_launch_forward(h->mt, X, B, s);
+    if (e == hipSuccess) e = hydro_mlp_launch_grad(h->mt, T, B, loss, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grad, h->mt.grad, sizeof(float) * mlp::NPAR, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "network gradient");
+}
+
+int hydro_mlp_train_step(hydro_t *h, const float *X, const float *T, int B, double lr, float *loss,
+                         void *stream) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = check_batch(h, X, B);
+    if (rc) return rc;
+    if (!T) return fail(h, HYDRO_EINVAL, "null targets");
+    if (!(lr > 0.0) || !isfinite(lr)) return fail(h, HYDRO_EINVAL, "lr must be > 0");
+    if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
+    if ((rc = set_device(h))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const double b1 = 0.9, b2 = 0.999;
+    ++h->adam_t;
+    const float c1 = (float)(1.0 - pow(b1, h->adam_t)), c2 = (float)(1.0 - pow(b2, h->adam_t));
+    hipError_t e = hydro_mlp_launch_forward(h->mt, X, B, s);
+    if (e == hipSuccess) e = hydro_mlp_launch_grad(h->mt, T, B, loss, s);
+    if (e == hipSuccess) e = hydro_mlp_launch_adam(h->mt, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2, s);
+    if (e == hipSuccess) e = hydro_mlp_launch_pack(h->mt, s);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "network train step");
+}
+
+int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t *valid) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !X || !T || !valid) return fail(h, HYDRO_EINVAL, "null U or pair buffer");
+    if ((rc = set_device(h))) return rc;
+    hipError_t e = hydro_launch_pairs(g->U, g->ghost_map, g->n, X, T, valid, (hipStream_t)g->stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "pairs launch");
+}
+
+int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback) {
+    if (!h) return HYDRO_EINVAL;
+    int rc = set_device(h);
+    if (rc) return rc;
+    unsigned long long fb = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&fb, h->fb_count, sizeof fb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(h->fb_count, 0, sizeof fb);
+    if (e != hipSuccess) return hip_fail(h, e, "network statistics");
+    if (cells) *cells = h->mlp_cells;
+    if (fallback) *fallback = (int64_t)fb;
+    h->mlp_cells = 0;
     return HYDRO_OK;
 }
 

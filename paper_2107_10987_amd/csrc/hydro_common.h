@@ -58,6 +58,10 @@ struct StageArgs {
     int *queue;               // [2]: next item, workgroups finished (zero between launches)
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
+    // learned reconstruction (null: plain PPM)
+    const float *mlp_y;       // [n][896][7][26]
+    const double *mlp_sigma;  // [n][896][7]
+    const uint8_t *mlp_ok;    // [n][896]
 };
 
 enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
@@ -69,5 +73,7 @@ hipError_t hydro_upload_ghost_table(const uint16_t *table);
 hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
                            hipStream_t s);
+hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,
+                              uint8_t *valid, hipStream_t s);
 hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,
                                     hipStream_t s);

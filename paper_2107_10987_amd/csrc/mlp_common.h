@@ -1,0 +1,63 @@
+// Shared definitions of the learned-reconstruction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hydro {
+namespace mlp {
+
+constexpr int IN = 34, HID = 64, OUT = 26, NPAR = 8090;
+// offsets in the float32 parameter vector
+constexpr int P_W1 = 0, P_B1 = 2176, P_W2 = 2240, P_B2 = 6336, P_W3 = 6400, P_B3 = 8064;
+// offsets in the bf16 MFMA copies: W1p[64][64], W2[64][64], W3p[32][64]
+constexpr int WB_W1 = 0, WB_W2 = 4096, WB_W3 = 8192, WB_SIZE = 10240;
+// transposed copies for the backward pass: W2T[64][64], W3T[64][64]
+constexpr int WB_W2T = 0, WB_W3T = 4096, WBT_SIZE = 8192;
+// cells whose reconstruction a leaf's fluxes need: 512 interior + 6 x 64
+// ghost cells sharing a face with the leaf
+constexpr int NSLOT = 896;
+
+// Slot of a needed cell (i, j, k in -1..8, at most one coordinate outside
+// 0..7): interior cells by linear index; face-adjacent ghost cells after them,
+// slab x-, x+, y-, y+, z-, z+, each by its two in-leaf coordinates in axis order.
+__host__ __device__ inline int slot_of(int i, int j, int k) {
+    if (i >= 0 && i < 8 && j >= 0 && j < 8 && k >= 0 && k < 8) return (k * 8 + j) * 8 + i;
+    if (i < 0 || i > 7) return 512 + 64 * (i < 0 ? 0 : 1) + j + 8 * k;
+    if (j < 0 || j > 7) return 512 + 64 * (j < 0 ? 2 : 3) + i + 8 * k;
+    return 512 + 64 * (k < 0 ? 4 : 5) + i + 8 * j;
+}
+
+struct MlpTrain {
+    float *par, *m, *v, *grad;          // [NPAR]
+    uint16_t *wb, *wbT;                 // bf16 MFMA copies
+    uint16_t *xb, *a1, *a2, *dz1, *dz2; // [B][64] bf16
+    float *z1, *z2, *dz1f, *dz2f;       // [B][64]
+    float *y, *dy;                      // [B][32]
+    float *loss_rows;                   // [B]
+};
+
+struct MlpInfer {
+    const double *U;            // [n][7][512]
+    const int32_t *gmap;        // [n][2232]
+    const uint16_t *ghost_pad;  // [2232] padded index of each ghost slot
+    const uint16_t *wb;         // bf16 weights
+    const float *par;           // float32 parameters (biases)
+    float *y;                   // [n][896][7][26]
+    double *sigma;              // [n][896][7]
+    uint8_t *cell_ok;           // [n][896]
+    unsigned long long *fb_count;  // cells that fell back to plain PPM
+    int leaf0;
+};
+
+}  // namespace mlp
+}  // namespace hydro
+
+hipError_t hydro_mlp_upload_slots(const uint16_t *slot_cell12);
+hipError_t hydro_mlp_launch_infer(const hydro::mlp::MlpInfer &m, int nleaf, hipStream_t s);
+hipError_t hydro_mlp_launch_pack(const hydro::mlp::MlpTrain &t, hipStream_t s);
+hipError_t hydro_mlp_launch_forward(const hydro::mlp::MlpTrain &t, const float *X, int B, hipStream_t s);
+hipError_t hydro_mlp_launch_grad(const hydro::mlp::MlpTrain &t, const float *T, int B, float *loss,
+                                 hipStream_t s);
+hipError_t hydro_mlp_launch_adam(const hydro::mlp::MlpTrain &t, float lr, float b1, float b2, float eps,
+                                 float c1, float c2, hipStream_t s);

@@ -1,0 +1,471 @@
+// Learned reconstruction on gfx950: a 34-64-64-26 tanh-GELU network on
+// normalised 3x3x3 neighbourhoods, bfloat16 operands and FP32 accumulation on
+// v_mfma_f32_16x16x16_bf16, with every value that reaches the FP64 scheme
+// checked in FP64 (neighbour bounds, per-line PPM monotonicity, positivity).
+//
+// Parameter vector (float32 masters, 8090 values): W1[64][34], b1[64],
+// W2[64][64], b2[64], W3[26][64], b3[26].  The MFMA copies are bfloat16,
+// zero-padded to W1p[64][64] and W3p[32][64].
+//
+// MFMA operand layout of the 16x16x16 bf16 instruction (lane l, q = l / 16):
+//   A[m][k]: lane holds m = l % 16, k = 4q .. 4q+3
+//   B[k][n]: lane holds n = l % 16, k = 4q .. 4q+3
+//   D[m][n]: lane holds n = l % 16, m = 4q .. 4q+3
+
+#include "hydro_common.h"
+#include "mlp_common.h"
+
+#include <math.h>
+
+using namespace hydro;
+using namespace hydro::mlp;
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// binary32 -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+constexpr float GELU_C = 0.7978845608028654f;
+constexpr float GELU_A = 0.044715f;
+
+__device__ __forceinline__ float gelu(float z) {
+    return 0.5f * z * (1.0f + tanhf(GELU_C * (z + GELU_A * z * z * z)));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float t = tanhf(GELU_C * (z + GELU_A * z * z * z));
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * GELU_C * (1.0f + 3.0f * GELU_A * z * z);
+}
+
+// One layer for a wave's 64 rows: Z[r][n] = sum_k A[r][k] W[n][k] + b[n],
+// A in LDS (bf16, row stride 64), W bf16 [NT*16][64] in global memory.
+// Results in D layout: z[mt][nt] holds rows 16 mt + 4q + i, column 16 nt + l%16.
+template <int NTILE>
+__device__ __forceinline__ void layer(const uint16_t *A, const uint16_t *W, int lane, v4f z[4][NTILE]) {
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTILE; ++nt) z[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        v4s b[NTILE];
+#pragma unroll
+        for (int nt = 0; nt < NTILE; ++nt)
+            b[nt] = *(const v4s *)(W + (16 * nt + r) * 64 + 16 * kb + 4 * q);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const v4s a = *(const v4s *)(A + (16 * mt + r) * 64 + 16 * kb + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < NTILE; ++nt) z[mt][nt] = mfma(a, b[nt], z[mt][nt]);
+        }
+    }
+}
+
+// Bias, GELU and bfloat16 rounding of a hidden layer back into the staging
+// buffer S (rows x 64); optionally keeps z (FP32) and a (bf16) per row in
+// global memory for the backward pass.
+__device__ __forceinline__ void hidden_out(v4f z[4][4], const float *bias, uint16_t *S, int lane,
+                                           float *zsave, uint16_t *asave, int row0, int nrows) {
+    const int c = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
+                const float zz = z[mt][nt][i] + bias[col];
+                const uint16_t a = bf16_bits(gelu(zz));
+                S[row * 64 + col] = a;
+                if (zsave && row < nrows) {
+                    zsave[(size_t)(row0 + row) * 64 + col] = zz;
+                    asave[(size_t)(row0 + row) * 64 + col] = a;
+                }
+            }
+}
+
+// Forward pass of the 64 rows staged (as bf16 inputs) in S; the 26 outputs of
+// row r land in Y[r][0..25] (FP32, stride 32, aliasing S).
+__device__ __forceinline__ void forward64(uint16_t *S, const uint16_t *Wb, const float *par, int lane,
+                                          float *z1s, uint16_t *a1s, float *z2s, uint16_t *a2s, int row0,
+                                          int nrows) {
+    v4f z[4][4];
+    layer<4>(S, Wb + WB_W1, lane, z);
+    hidden_out(z, par + P_B1, S, lane, z1s, a1s, row0, nrows);
+    layer<4>(S, Wb + WB_W2, lane, z);
+    hidden_out(z, par + P_B2, S, lane, z2s, a2s, row0, nrows);
+    v4f y[4][2];
+    layer<2>(S, Wb + WB_W3, lane, y);
+    float *Y = (float *)S;
+    const int c = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
+                if (col < OUT) Y[row * 32 + col] = y[mt][nt][i] + par[P_B3 + col];
+            }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Training
+// ---------------------------------------------------------------------------
+
+// Forward of B rows of X [B][34] (float32); keeps what the backward needs.
+__global__ void __launch_bounds__(256) mlp_train_forward(MlpTrain t, const float *X, int B) {
+    __shared__ uint16_t S[4][64 * 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row0 = (blockIdx.x * 4 + w) * 64;
+    if (row0 >= B) return;                        // wave-uniform
+    const int nrows = B - row0 < 64 ? B - row0 : 64;
+    uint16_t *s = S[w];
+    // row `lane`: inputs rounded to bf16, zero padding beyond 34 and beyond B
+    for (int k = 0; k < 64; ++k) {
+        const float v = (lane < nrows && k < IN) ? X[(size_t)(row0 + lane) * IN + k] : 0.f;
+        const uint16_t b = bf16_bits(v);
+        s[lane * 64 + k] = b;
+        if (lane < nrows) t.xb[(size_t)(row0 + lane) * 64 + k] = b;
+    }
+    forward64(s, t.wb, t.par, lane, t.z1, t.a1, t.z2, t.a2, row0, nrows);
+    const float *Y = (const float *)s;
+    if (lane < nrows)
+        for (int o = 0; o < OUT; ++o) t.y[(size_t)(row0 + lane) * 32 + o] = Y[lane * 32 + o];
+}
+
+// dY = 2 (y - T) / (B * 26); dZ2 = (dY W3) * gelu'(z2); dZ1 = (dZ2 W2) * gelu'(z1).
+// One wave per 64 rows; per-row loss partials.
+__global__ void __launch_bounds__(256) mlp_train_backward_rows(MlpTrain t, const float *T, int B) {
+    __shared__ uint16_t S[4][64 * 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row0 = (blockIdx.x * 4 + w) * 64;
+    if (row0 >= B) return;
+    const int nrows = B - row0 < 64 ? B - row0 : 64;
+    uint16_t *s = S[w];
+    const float scale = 2.0f / ((float)B * OUT);
+    float loss = 0.f;
+    for (int o = 0; o < 64; ++o) {
+        float d = 0.f;
+        if (lane < nrows && o < OUT) {
+            const float r = t.y[(size_t)(row0 + lane) * 32 + o] - T[(size_t)(row0 + lane) * OUT + o];
+            loss += r * r;
+            d = scale * r;
+            t.dy[(size_t)(row0 + lane) * 32 + o] = d;
+        }
+        s[lane * 64 + o] = bf16_bits(d);   // dY as the A operand (k = output index)
+    }
+    if (lane < nrows) t.loss_rows[row0 + lane] = loss;
+    // dA2[r][h] = sum_o dY[r][o] W3[o][h]: B operand[k = o][n = h] = W3[o][h] -> W3T copy
+    v4f z[4][4];
+    layer<4>(s, t.wbT + WB_W3T, lane, z);
+    const int c = lane & 15, q = lane >> 4;
+    // dZ2 = dA2 * gelu'(z2) -> bf16 into s (A operand of the next product) and global
+    for (int mt = 0; mt < 4; ++mt)
+        for (int nt = 0; nt < 4; ++nt)
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
+                float d = 0.f;
+                if (row < nrows) d = z[mt][nt][i] * gelu_grad(t.z2[(size_t)(row0 + row) * 64 + col]);
+                if (row < nrows) t.dz2f[(size_t)(row0 + row) * 64 + col] = d;
+                const uint16_t b = bf16_bits(d);
+                s[row * 64 + col] = b;
+                if (row < nrows) t.dz2[(size_t)(row0 + row) * 64 + col] = b;
+            }
+    layer<4>(s, t.wbT + WB_W2T, lane, z);
+    for (int mt = 0; mt < 4; ++mt)
+        for (int nt = 0; nt < 4; ++nt)
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
+                if (row < nrows) {
+                    const float d = z[mt][nt][i] * gelu_grad(t.z1[(size_t)(row0 + row) * 64 + col]);
+                    t.dz1f[(size_t)(row0 + row) * 64 + col] = d;
+                    t.dz1[(size_t)(row0 + row) * 64 + col] = bf16_bits(d);
+                }
+            }
+}
+
+// Weight gradients dW[m][n] = sum_b dZ[b][m] A[b][n] by MFMA, one wave per
+// 16x16 tile, reducing over all B rows in a fixed order (deterministic);
+// bias gradients by lanes summing columns of the FP32 dZ in row order.
+// Tiles: W3 (26x64 -> 2x4), W2 (4x4), W1 (64x34 -> 4x3 of the padded 64x48).
+__global__ void __launch_bounds__(64) mlp_train_wgrad(MlpTrain t, int B) {
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x;
+    const uint16_t *dZ, *A;
+    int mt, nt, ldz, gofs, mrows, ncols;
+    if (tile < 8) {            // W3: dZ = dY (bf16 copy), A = a2
+        dZ = nullptr; A = t.a2; mt = tile / 4; nt = tile % 4; ldz = 32; gofs = P_W3; mrows = OUT; ncols = HID;
+    } else if (tile < 24) {    // W2: dZ = dZ2, A = a1
+        dZ = t.dz2; A = t.a1; mt = (tile - 8) / 4; nt = (tile - 8) % 4; ldz = 64; gofs = P_W2; mrows = HID; ncols = HID;
+    } else {                   // W1: dZ = dZ1, A = x
+        dZ = t.dz1; A = t.xb; mt = (tile - 24) / 3; nt = (tile - 24) % 3; ldz = 64; gofs = P_W1; mrows = HID; ncols = IN;
+    }
+    const int r = lane & 15, q = lane >> 4;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int b0 = 0; b0 < B; b0 += 16) {
+        // A operand [m][k = batch]: dZ[b0 + 4q + i][16 mt + r]
+        v4s a, bb;
+        for (int i = 0; i < 4; ++i) {
+            const int row = b0 + 4 * q + i;
+            uint16_t va = 0, vb = 0;
+            if (row < B) {
+                const int m = 16 * mt + r, n = 16 * nt + r;
+                if (m < mrows) va = dZ ? dZ[(size_t)row * ldz + m] : bf16_bits(t.dy[(size_t)row * 32 + m]);
+                vb = A[(size_t)row * 64 + n];
+            }
+            a[i] = (short)va;
+            bb[i] = (short)vb;
+        }
+        acc = mfma(a, bb, acc);
+    }
+    for (int i = 0; i < 4; ++i) {
+        const int m = 16 * mt + 4 * q + i, n = 16 * nt + r;
+        if (m < mrows && n < ncols) t.grad[gofs + m * ncols + n] = acc[i];
+    }
+    // bias gradients: the first tile of each matrix's row block sums columns
+    if (nt == 0 && lane < 16) {
+        const int m = 16 * mt + lane;
+        if (m < mrows) {
+            float s = 0.f;
+            for (int b = 0; b < B; ++b)
+                s += (tile < 8) ? t.dy[(size_t)b * 32 + m]
+                                : (tile < 24 ? t.dz2f[(size_t)b * 64 + m] : t.dz1f[(size_t)b * 64 + m]);
+            const int bofs = tile < 8 ? P_B3 : (tile < 24 ? P_B2 : P_B1);
+            t.grad[bofs + m] = s;
+        }
+    }
+}
+
+// Loss = sum of per-row partials / (B * 26), summed in row order.
+__global__ void __launch_bounds__(64) mlp_loss_reduce(MlpTrain t, int B, float *loss_out) {
+    __shared__ float red[64];
+    float s = 0.f;
+    for (int b = threadIdx.x; b < B; b += 64) s += t.loss_rows[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float tot = 0.f;
+        for (int i = 0; i < 64; ++i) tot += red[i];
+        *loss_out = tot / ((float)B * OUT);
+    }
+}
+
+// Adam on the float32 masters, then the bf16 MFMA copies (plain and
+// transposed, zero padded).
+__global__ void __launch_bounds__(256) mlp_adam(MlpTrain t, float lr, float b1, float b2, float eps,
+                                                float c1, float c2) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= NPAR) return;
+    const float g = t.grad[i];
+    const float m = b1 * t.m[i] + (1.f - b1) * g;
+    const float v = b2 * t.v[i] + (1.f - b2) * g * g;
+    t.m[i] = m;
+    t.v[i] = v;
+    t.par[i] = t.par[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// bf16 copies of the weights: W1p[64][64], W2[64][64], W3p[32][64] and the
+// transposes used by the backward pass, W2T[64][64], W3T[64][64] (k = output).
+__global__ void __launch_bounds__(256) mlp_pack(MlpTrain t) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 64 * 64) return;
+    const int n = i / 64, k = i % 64;
+    t.wb[WB_W1 + i] = bf16_bits(k < IN ? t.par[P_W1 + n * IN + k] : 0.f);
+    t.wb[WB_W2 + i] = bf16_bits(t.par[P_W2 + n * HID + k]);
+    if (n < 32) t.wb[WB_W3 + i] = bf16_bits(n < OUT ? t.par[P_W3 + n * HID + k] : 0.f);
+    // transposes: W2T[h][k2] = W2[k2][h]; W3T[h][o] = W3[o][h] (o < 26, else 0)
+    t.wbT[WB_W2T + i] = bf16_bits(t.par[P_W2 + k * HID + n]);
+    t.wbT[WB_W3T + i] = bf16_bits(k < OUT ? t.par[P_W3 + k * HID + n] : 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// Inference pre-pass of a stage: every needed cell of every leaf
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int RB12 = 12;   // cells -2..9 per axis: the 3x3x3 neighbourhoods of cells -1..8
+
+__constant__ uint16_t c_slot_cell[NSLOT];   // needed cell slot -> 12^3 index of the cell
+
+__device__ __forceinline__ int p12(int i, int j, int k) { return ((k + 2) * RB12 + (j + 2)) * RB12 + (i + 2); }
+
+// FP64 acceptance test of one row (same expressions as the oracle's).
+__device__ __forceinline__ bool row_ok(const double nb[27], const double val[26], int f) {
+    const double qc = nb[13];
+    bool ok = true;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        if (o == 13) continue;
+        const int d = o < 13 ? o : o - 1;
+        const double qn = nb[o], v = val[d];
+        const double lo = qc < qn ? qc : qn, hi = qc < qn ? qn : qc;
+        ok = ok && (v >= lo && v <= hi);
+        if (f == RHO || f == EGAS || f == TAU) ok = ok && (v > 0.0);
+        if (f == SPC) ok = ok && (v >= 0.0);
+    }
+    const int lines[13] = {14, 16, 22, 17, 11, 23, 5, 25, 7, 26, 8, 20, 2};   // dir27 of +d
+#pragma unroll
+    for (int l = 0; l < 13; ++l) {
+        const int op = lines[l], om = 26 - op;
+        const double R = val[op < 13 ? op : op - 1], L = val[om < 13 ? om : om - 1];
+        if (L == qc && R == qc) continue;
+        const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
+        const double lim = D * D + 1e-13 * fabs(D) * (fabs(L) + fabs(qc) + fabs(R));
+        ok = ok && ((R - qc) * (qc - L) > 0.0) && !(D * M6 > lim) && !(D * M6 < -lim);
+    }
+    return ok;
+}
+
+}  // namespace
+
+// One workgroup per leaf: stage cells -2..9 of every field in LDS, then each
+// wave takes chunks of 9 cells x 7 fields = 63 rows (lane = row): FP64
+// features, the network on MFMA, FP64 denormalisation and check.  Writes the
+// outputs y (FP32), sigma (FP64) and a per-cell pass flag.
+__global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
+    __shared__ double B12[NF * RB12 * RB12 * RB12];      // 96,768 B
+    __shared__ uint16_t S[4][64 * 64];                   // 32,768 B
+    const int leaf = m.leaf0 + blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // gather: interior from U, the rest through the ghost map (skipping the
+    // outermost ghost layer, which no 3x3x3 neighbourhood of a needed cell reads)
+    const double *Ul = m.U + (size_t)leaf * LEAF_STRIDE;
+    for (int e = tid; e < LEAF_STRIDE; e += 256) {
+        const int f = e >> 9, c = e & (NC - 1);
+        B12[f * 1728 + p12(c & 7, (c >> 3) & 7, c >> 6)] = Ul[e];
+    }
+    const int32_t *gm = m.gmap + (size_t)leaf * NG;
+    for (int s = tid; s < NG; s += 256) {
+        const int pp = m.ghost_pad[s];
+        const int gi = pp % PB - GW, gj = (pp / PB) % PB - GW, gk = pp / (PB * PB) - GW;
+        if (gi < -2 || gi > 9 || gj < -2 || gj > 9 || gk < -2 || gk > 9) continue;
+        const int src = gm[s];
+        const int b = src >= 0 ? src : -src - 1;
+        const double *q = m.U + (size_t)(b >> 9) * LEAF_STRIDE + (b & (NC - 1));
+        for (int f = 0; f < NF; ++f) {
+            double v;
+            if (src >= 0) {
+                v = q[f * NC];
+            } else {
+                const double *qf = q + f * NC;
+                double acc = 0.0;
+                acc = acc + qf[0];
+                acc = acc + qf[1];
+                acc = acc + qf[8];
+                acc = acc + qf[9];
+                acc = acc + qf[64];
+                acc = acc + qf[65];
+                acc = acc + qf[72];
+                acc = acc + qf[73];
+                v = acc * 0.125;
+            }
+            B12[f * 1728 + p12(gi, gj, gk)] = v;
+        }
+    }
+    __syncthreads();
+    uint16_t *s = S[w];
+    float *ys = (float *)s;
+    for (int chunk = w; chunk < (NSLOT + 8) / 9; chunk += 4) {
+        const int slot = 9 * chunk + lane / 7, f = lane - 7 * (lane / 7);
+        const bool live = lane < 63 && slot < NSLOT;
+        double nb[27], sigma = 0.0;
+        const int c12 = c_slot_cell[live ? slot : 0];
+        const double *q = B12 + f * 1728;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    nb[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)] = q[c12 + dx + RB12 * dy + RB12 * RB12 * dz];
+        const double qc = nb[13];
+#pragma unroll
+        for (int o = 0; o < 27; ++o) {
+            const double a = fabs(nb[o] - qc);
+            sigma = a > sigma ? a : sigma;
+        }
+        const bool flat = !(sigma > 0.0);
+        const double rs = flat ? 0.0 : 1.0 / sigma;
+        for (int k = 0; k < 64; ++k) {
+            float v = 0.f;
+            if (k < 27) v = (float)((nb[k] - qc) * rs);
+            else if (k < IN) v = (k - 27 == f) ? 1.f : 0.f;
+            s[lane * 64 + k] = (live && !flat) ? bf16_bits(v) : (uint16_t)0;
+        }
+        forward64(s, m.wb, m.par, lane, nullptr, nullptr, nullptr, nullptr, 0, 0);
+        double val[26];
+        float yv[26];
+#pragma unroll
+        for (int d = 0; d < 26; ++d) {
+            yv[d] = flat ? 0.f : ys[lane * 32 + d];
+            val[d] = flat ? qc : qc + sigma * (double)yv[d];
+        }
+        const bool ok = !live || flat || row_ok(nb, val, f);
+        const unsigned long long mask = __ballot(ok);
+        // count the cells that fall back to plain PPM (lane 7m holds cell m)
+        const bool cell_fails = live && f == 0 && ((mask >> (7 * (lane / 7))) & 0x7fu) != 0x7fu;
+        const unsigned long long fails = __ballot(cell_fails);
+        if (lane == 0 && fails) atomicAdd(m.fb_count, (unsigned long long)__popcll(fails));
+        if (live) {
+            const size_t row = ((size_t)leaf * NSLOT + slot) * NF + f;
+#pragma unroll
+            for (int d = 0; d < 26; ++d) m.y[row * 26 + d] = yv[d];
+            m.sigma[row] = flat ? 0.0 : sigma;
+            if (f == 0) {
+                const unsigned bits = (unsigned)((mask >> (7 * (lane / 7))) & 0x7fu);
+                m.cell_ok[(size_t)leaf * NSLOT + slot] = bits == 0x7fu ? 1 : 0;
+            }
+        }
+    }
+}
+
+hipError_t hydro_mlp_upload_slots(const uint16_t *slot_cell12) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_slot_cell), slot_cell12, sizeof(uint16_t) * NSLOT);
+}
+
+hipError_t hydro_mlp_launch_infer(const MlpInfer &m, int nleaf, hipStream_t s) {
+    if (nleaf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3(nleaf), dim3(256), 0, s, m);
+    return hipGetLastError();
+}
+
+hipError_t hydro_mlp_launch_pack(const MlpTrain &t, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_pack, dim3(16), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+hipError_t hydro_mlp_launch_forward(const MlpTrain &t, const float *X, int B, hipStream_t s) {
+    const int waves = (B + 63) / 64;
+    hipLaunchKernelGGL(mlp_train_forward, dim3((waves + 3) / 4), dim3(256), 0, s, t, X, B);
+    return hipGetLastError();
+}
+
+hipError_t hydro_mlp_launch_grad(const MlpTrain &t, const float *T, int B, float *loss, hipStream_t s) {
+    const int waves = (B + 63) / 64;
+    hipLaunchKernelGGL(mlp_train_backward_rows, dim3((waves + 3) / 4), dim3(256), 0, s, t, T, B);
+    hipLaunchKernelGGL(mlp_train_wgrad, dim3(8 + 16 + 12), dim3(64), 0, s, t, B);
+    if (loss) hipLaunchKernelGGL(mlp_loss_reduce, dim3(1), dim3(64), 0, s, t, B, loss);
+    return hipGetLastError();
+}
+
+hipError_t hydro_mlp_launch_adam(const MlpTrain &t, float lr, float b1, float b2, float eps, float c1,
+                                 float c2, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s, t, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}

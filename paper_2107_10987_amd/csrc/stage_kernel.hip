@@ -20,6 +20,7 @@
 // results round exactly as the expressions are written.
 
 #include "hydro_common.h"
+#include "mlp_common.h"
 
 #include <math.h>
 
@@ -376,6 +377,34 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
     }
 }
 
+// Where a lane's point values come from: plain PPM, or (learned
+// reconstruction, cell passed the FP64 check) q_c + sigma * y from the
+// inference pre-pass.
+struct ValSrc {
+    const float *y;        // [7][26] of this cell, or null for plain PPM
+    const double *sigma;   // [7]
+};
+
+__device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
+    const int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    return k < 13 ? k : k - 1;
+}
+
+__device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy, int dz,
+                                          const ValSrc &src, double pos[NF], double neg[NF]) {
+    if (src.y) {
+        const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double qc = P[f * NP + c], sg = src.sigma[f];
+            pos[f] = qc + sg * (double)src.y[f * 26 + dp];
+            neg[f] = qc + sg * (double)src.y[f * 26 + dm];
+        }
+    } else {
+        line_ends(P, c, dx, dy, dz, pos, neg);
+    }
+}
+
 __device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double shfl_down1(double v) { return __shfl_down(v, 1, 64); }
 
@@ -402,13 +431,22 @@ __device__ __forceinline__ double point_flux_acc(const double UL[NF], const doub
 template <int N>
 __device__ __forceinline__ void column_axis(const double *P, int col, int cell, double dx,
                                             double ox, double oy, double oz, const Phys &ph,
-                                            double dsum[NF], double &smax) {
+                                            const StageArgs &a, int leaf, double dsum[NF],
+                                            double &smax) {
     const int c1 = col & 7, c2 = col >> 3;
     // cell B on the walk, in (x, y, z): axis N takes `cell`, t1 < t2 take c1, c2
     const int bi = (N == 0) ? cell : c1;
     const int bj = (N == 1) ? cell : ((N == 0) ? c1 : c2);
     const int bk = (N == 2) ? cell : c2;
     const int cB = pidx(bi, bj, bk);
+    ValSrc src{nullptr, nullptr};
+    if (a.mlp_y) {
+        const size_t row = (size_t)leaf * mlp::NSLOT + mlp::slot_of(bi, bj, bk);
+        if (a.mlp_ok[row]) {
+            src.y = a.mlp_y + row * NF * 26;
+            src.sigma = a.mlp_sigma + row * NF;
+        }
+    }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;
     (void)oz;
@@ -425,7 +463,7 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
     auto qy = [&](int a, int b) { return yB + 0.5 * (double)((N == 1) ? -1 : ((N == 0) ? a : b)) * dx; };
     {   // the face-normal line serves the face centre
         double pos[NF], neg[NF], prev[NF];
-        line_ends(P, cB, dirx(0, 0), diry(0, 0), dirz(0, 0), pos, neg);
+        line_vals(P, cB, dirx(0, 0), diry(0, 0), dirz(0, 0), src, pos, neg);
 #pragma unroll
         for (int f = 0; f < NF; ++f) prev[f] = shfl_up1(pos[f]);
         if (face) {
@@ -440,8 +478,8 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
         const int b = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
         const double w = (p < 2) ? 4.0 / 36.0 : 1.0 / 36.0;
         double pos1[NF], neg1[NF], pos2[NF], neg2[NF];
-        line_ends(P, cB, dirx(a, b), diry(a, b), dirz(a, b), pos1, neg1);
-        line_ends(P, cB, dirx(-a, -b), diry(-a, -b), dirz(-a, -b), pos2, neg2);
+        line_vals(P, cB, dirx(a, b), diry(a, b), dirz(a, b), src, pos1, neg1);
+        line_vals(P, cB, dirx(-a, -b), diry(-a, -b), dirz(-a, -b), src, pos2, neg2);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             pos1[f] = shfl_up1(pos1[f]);
@@ -487,7 +525,7 @@ __device__ __forceinline__ void col_axis_to_ws(const StageArgs &a, const double 
     const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
     double d[NF];
     double sm = 0.0;
-    column_axis<N>(P, L.col, L.cell, dx, ox, oy, oz, a.ph, d, sm);
+    column_axis<N>(P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, d, sm);
     smax = L.live && sm > smax ? sm : smax;
     if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
         const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
@@ -656,6 +694,56 @@ hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(stage_kernel_col_persistent, dim3(grid), dim3(NTC), 0, s, a);
     }
     }
+    return hipGetLastError();
+}
+
+// Training pairs of the learned reconstruction from the plain one: for each
+// interior cell and field, the normalised 3x3x3 neighbourhood with the field's
+// one-hot id (X [.][34], FP32 of the FP64 values) and the plain PPM values at
+// the 26 points in the same normalisation (T [.][26]); rows are
+// [leaf][cell][field], and valid = 0 marks flat neighbourhoods (sigma = 0).
+__global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_t *gm, float *X,
+                                                   float *T, uint8_t *valid) {
+    __shared__ double P[NF * NP];
+    const int leaf = blockIdx.x;
+    gather_block(P, U, gm, leaf, threadIdx.x, NT);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NC * NF; e += NT) {
+        const int c = e / NF, f = e - (e / NF) * NF;
+        const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+        const int pc = pidx(i, j, k);
+        const double *q = P + f * NP;
+        const double qc = q[pc];
+        double sigma = 0.0;
+        for (int o = 0; o < 27; ++o) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            const double d = fabs(q[pc + dx * SX_ + dy * SY_ + dz * SZ_] - qc);
+            sigma = d > sigma ? d : sigma;
+        }
+        const size_t row = ((size_t)leaf * NC + c) * NF + f;
+        valid[row] = sigma > 0.0 ? 1 : 0;
+        const double rs = sigma > 0.0 ? 1.0 / sigma : 0.0;
+        for (int o = 0; o < 27; ++o) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            X[row * 34 + o] = (float)((q[pc + dx * SX_ + dy * SY_ + dz * SZ_] - qc) * rs);
+        }
+        for (int g = 0; g < NF; ++g) X[row * 34 + 27 + g] = (g == f) ? 1.f : 0.f;
+        for (int o = 0; o < 27; ++o) {
+            if (o == 13) continue;
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            const bool plus = (dx != 0) ? (dx > 0) : ((dy != 0) ? (dy > 0) : (dz > 0));
+            int st = dx * SX_ + dy * SY_ + dz * SZ_;
+            st = plus ? st : -st;
+            const double v = ppm_end(q, pc, st, plus);
+            T[row * 26 + (o < 13 ? o : o - 1)] = (float)((v - qc) * rs);
+        }
+    }
+}
+
+hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,
+                              uint8_t *valid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pairs_kernel, dim3(n), dim3(NT), 0, s, U, gm, X, T, valid);
     return hipGetLastError();
 }
 

@@ -19,7 +19,9 @@ NX, NF, NC, NGHOST = 8, 7, 512, 2232
 
 EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_step", "hydro_stage",
            "hydro_signal_speed", "hydro_reconstruct", "hydro_step_dev", "hydro_dt",
-           "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_amax_device",
+           "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_mlp_load",
+           "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
+           "hydro_mlp_pairs", "hydro_mlp_stats", "hydro_amax_device",
            "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error")
 SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
 NBUCKET = 16
@@ -34,7 +36,7 @@ class HydroError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
                 ("schedule", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
-                ("tune_cache", C.c_char_p)]
+                ("tune_cache", C.c_char_p), ("mlp_batch", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -74,6 +76,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_graph_capture.argtypes = [vp, C.POINTER(Grid), C.c_double, vp, C.c_int]
     L.hydro_graph_launch.argtypes = [vp, vp]
     L.hydro_autotune.argtypes = [vp, C.POINTER(Grid), C.c_char_p, C.POINTER(C.c_int32)]
+    fp = C.POINTER(C.c_float)
+    L.hydro_mlp_load.argtypes = [vp, fp]
+    L.hydro_mlp_save.argtypes = [vp, fp]
+    L.hydro_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+    L.hydro_mlp_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
+    L.hydro_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_double, vp, vp]
+    L.hydro_mlp_pairs.argtypes = [vp, C.POINTER(Grid), vp, vp, vp]
+    L.hydro_mlp_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.hydro_amax_device.argtypes = [vp]
     L.hydro_amax_device.restype = vp
     L.hydro_check.argtypes = [vp, vp]
@@ -109,18 +119,25 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def _sptr(stream):
+    return None if stream is None else (int(stream.cuda_stream) or None)
+
+
 class Hydro:
     """A library handle: owns the device workspace for up to ``max_leaves``."""
 
     def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
-                 schedule: str = "auto", tune_cache: str | None = None):
+                 schedule: str = "auto", tune_cache: str | None = None, learned: bool = False,
+                 mlp_batch: int = 4096):
         import torch
         self.torch = torch
         self.L = load()
         self.device = device
         self.schedule = schedule
-        self.p = Params(int(max_leaves), int(device), 0, SCHEDULES[schedule], float(eta1),
-                        float(eta2), tune_cache.encode() if tune_cache else None)
+        self.learned = learned
+        self.p = Params(int(max_leaves), int(device), int(bool(learned)), SCHEDULES[schedule],
+                        float(eta1), float(eta2), tune_cache.encode() if tune_cache else None,
+                        int(mlp_batch), 0)
         h = C.c_void_p()
         rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
         if rc:
@@ -179,6 +196,47 @@ class Hydro:
                                           cache_path.encode() if cache_path else None, table))
         inv = {v: k for k, v in SCHEDULES.items()}
         return [inv[v] for v in table]
+
+    # -- learned reconstruction ---------------------------------------------
+    def mlp_load(self, params):
+        par = np.ascontiguousarray(params, dtype=np.float32)
+        assert par.shape == (8090,)
+        self._check(self.L.hydro_mlp_load(self.h, par.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def mlp_save(self):
+        par = np.zeros(8090, dtype=np.float32)
+        self._check(self.L.hydro_mlp_save(self.h, par.ctypes.data_as(C.POINTER(C.c_float))))
+        return par
+
+    def mlp_forward(self, X, stream=None):
+        Y = self.torch.empty((X.shape[0], 26), dtype=self.torch.float32, device=X.device)
+        self._check(self.L.hydro_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y), _sptr(stream)))
+        return Y
+
+    def mlp_grad(self, X, T, stream=None):
+        g = self.torch.empty(8090, dtype=self.torch.float32, device=X.device)
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=X.device)
+        self._check(self.L.hydro_mlp_grad(self.h, _ptr(X), _ptr(T), X.shape[0], _ptr(g), _ptr(loss),
+                                          _sptr(stream)))
+        return g, loss
+
+    def mlp_train_step(self, X, T, lr: float, loss=None, stream=None):
+        self._check(self.L.hydro_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], float(lr),
+                                                _ptr(loss), _sptr(stream)))
+
+    def mlp_pairs(self, g: "DeviceGrid"):
+        n = g.n * NC * NF
+        t = self.torch
+        X = t.empty((n, 34), dtype=t.float32, device=g.U.device)
+        T = t.empty((n, 26), dtype=t.float32, device=g.U.device)
+        V = t.empty(n, dtype=t.uint8, device=g.U.device)
+        self._check(self.L.hydro_mlp_pairs(self.h, C.byref(g.c), _ptr(X), _ptr(T), _ptr(V)))
+        return X, T, V
+
+    def mlp_stats(self):
+        c, f = C.c_int64(), C.c_int64()
+        self._check(self.L.hydro_mlp_stats(self.h, C.byref(c), C.byref(f)))
+        return c.value, f.value
 
     def signal_speed(self, g: "DeviceGrid"):
         a = self.torch.empty(g.n, dtype=self.torch.float64, device=g.U.device)

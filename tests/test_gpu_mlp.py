@@ -1,0 +1,239 @@
+"""GPU tests of the learned reconstruction against the CPU oracle.
+
+The network's forward pass and gradients are compared with the oracle run in
+bfloat16-emulating mode (rel 1e-3 per tensor norm: bfloat16 operands carry 8
+significant bits and the two sides accumulate in different orders); training
+pairs are compared bit for bit (same FP64 expressions, one final rounding to
+FP32); the fallback path is held to the plain path's 1e-12 bar; conservation
+holds to round-off with the learned path on; and a report of what the trained
+network gains or loses against plain PPM on the batched polytrope."""
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd.workloads import (blast_single_leaf, rotating_polytrope, sedov_uniform,
+                                            uneven_batches)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _params(seed, scale=0.3):
+    return (np.random.default_rng(seed).normal(size=8090) * scale).astype(np.float32)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_forward_matches_oracle(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: network forward B=1000 (ragged)", flush=True)
+    p = _params(1)
+    X = np.random.default_rng(2).normal(size=(1000, 34)).astype(np.float32)
+    hy = Hydro(max_leaves=1)
+    try:
+        hy.mlp_load(p)
+        Y = hy.mlp_forward(torch.tensor(X, device="cuda")).cpu().numpy()
+    finally:
+        hy.close()
+    Yo = oracle.mlp_forward(p, X.astype(np.float64), emulate=True)
+    print("forward rel err", _rel(Y, Yo), flush=True)
+    assert _rel(Y, Yo) <= 1e-3
+
+
+def test_gradients_match_oracle(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: network gradients B=777", flush=True)
+    p = _params(3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(777, 34)).astype(np.float32)
+    T = rng.normal(size=(777, 26)).astype(np.float32)
+    hy = Hydro(max_leaves=1)
+    try:
+        hy.mlp_load(p)
+        g, loss = hy.mlp_grad(torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda"))
+        g, loss = g.cpu().numpy(), float(loss.item())
+    finally:
+        hy.close()
+    lo, go = oracle.mlp_loss_grad(p, X.astype(np.float64), T.astype(np.float64), emulate=True)
+    assert abs(loss - lo) <= 1e-4 * lo
+    for name, (off, shape) in oracle.MLP_SLICES.items():
+        n = int(np.prod(shape))
+        e = _rel(g[off:off + n], go[off:off + n])
+        print(f"grad {name} rel err {e:.2e}", flush=True)
+        assert e <= 1e-3, name
+
+
+def test_adam_step_matches_oracle(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    p = _params(5)
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(512, 34)).astype(np.float32)
+    T = rng.normal(size=(512, 26)).astype(np.float32)
+    hy = Hydro(max_leaves=1)
+    try:
+        hy.mlp_load(p)
+        hy.mlp_train_step(torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda"), 1e-3)
+        p_gpu = hy.mlp_save()
+    finally:
+        hy.close()
+    _, go = oracle.mlp_loss_grad(p, X.astype(np.float64), T.astype(np.float64), emulate=True)
+    p_ora = p.copy()
+    oracle.adam(p_ora, go, np.zeros(8090), np.zeros(8090), 1, lr=1e-3)
+    # the first Adam step moves every parameter by lr * sign(g); compare where
+    # the gradient is clearly away from zero
+    sel = np.abs(go) > 1e-2 * np.abs(go).max()
+    assert sel.sum() > 1000
+    assert np.max(np.abs((p_gpu - p)[sel] - (p_ora - p)[sel])) <= 1e-3 * 1e-3 + 1e-7
+
+
+def test_pairs_match_oracle_bitwise(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: training pairs, blast leaf after one step", flush=True)
+    w = blast_single_leaf()
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    P = o.padded(U)[0]
+    V = oracle.reconstruct_values(P)
+    hy = Hydro(max_leaves=1)
+    try:
+        g = hy.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        X, T, valid = (t.cpu().numpy() for t in hy.mlp_pairs(g))
+    finally:
+        hy.close()
+    for c in range(0, 512, 7):
+        i, j, k = c & 7, (c >> 3) & 7, c >> 6
+        for f in range(7):
+            row = c * 7 + f
+            nb, s, x = oracle.mlp_features(P, i, j, k, f)
+            assert valid[row] == (x is not None)
+            if x is None:
+                continue
+            assert np.array_equal(X[row], x.astype(np.float32))
+            cell = (k + 1) * 100 + (j + 1) * 10 + (i + 1)
+            t = ((V[cell, :, f] - nb[13]) * (1.0 / s)).astype(np.float32)
+            assert np.array_equal(T[row], t)
+
+
+def test_adversarial_bias_gives_the_plain_step(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: adversarial bias -> 100% fallback, sedov-32^3", flush=True)
+    w = sedov_uniform(4)
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    p = _params(7)
+    p[8064:] = 10.0
+    plain = Hydro(max_leaves=w.n, schedule="column")
+    lrn = Hydro(max_leaves=w.n, schedule="column", learned=True)
+    try:
+        lrn.mlp_load(p)
+        ga = plain.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        gb = lrn.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        dt = 2e-4
+        aa = plain.step(ga, dt)
+        ab = lrn.step(gb, dt)
+        cells, fb = lrn.mlp_stats()
+        print("fallback", fb, "of", cells, flush=True)
+        assert torch.equal(ga.U, gb.U) and np.array_equal(aa, ab)
+        Uo, _, fbo = o.step_learned(p, dt, U)
+        err = np.abs(gb.U.cpu().numpy() - Uo).reshape(w.n, 7, -1).max(axis=(0, 2))
+        scale = np.abs(Uo).reshape(w.n, 7, -1).max(axis=(0, 2))
+        assert np.all(err <= 1e-12 * scale)
+    finally:
+        plain.close()
+        lrn.close()
+
+
+def _quick_params(torch):
+    from paper_2107_10987_amd import learned
+    X, T = learned.collect_pairs(torch, sedov_steps=6, leaves_per_axis=4)
+    Xs, Ts = learned.sample(torch, X, T, 2 ** 17)
+    from paper_2107_10987_amd.hydro import Hydro
+    hy = Hydro(max_leaves=1)
+    try:
+        params, hist = learned.train(torch, hy, Xs, Ts, epochs=3, log=lambda h: print(h, flush=True))
+    finally:
+        hy.close()
+    assert hist[-1]["train_loss"] < hist[0]["train_loss"] or hist[-1]["train_loss"] < 1e-3
+    return params
+
+
+@pytest.fixture(scope="module")
+def trained(torch):
+    print("case: quick training (2^17 pairs, 3 epochs)", flush=True)
+    return _quick_params(torch)
+
+
+def test_learned_step_conserves_and_tracks_oracle(torch, trained):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: learned step on the blast leaf vs oracle", flush=True)
+    w = blast_single_leaf()
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    dt = o.dt(U)
+    hy = Hydro(max_leaves=1, schedule="column", learned=True)
+    try:
+        hy.mlp_load(trained)
+        g = hy.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        hy.step(g, dt)
+        cells, fb = hy.mlp_stats()
+        got = g.U.cpu().numpy()
+    finally:
+        hy.close()
+    for f in (0, 4, 6):
+        assert abs(got[:, f].sum() - U[:, f].sum()) <= 1e-14 * np.abs(U[:, f]).sum()
+    Uo, _, fbo = o.step_learned(trained, dt, U)
+    Up, _ = o.step(dt, U)
+    dev_oracle = np.abs(got - Uo).max() / np.abs(Uo).max()
+    dev_plain = np.abs(got - Up).max() / np.abs(Up).max()
+    print(f"fallback gpu {fb}/{cells}, oracle {int(fbo.sum())}; max rel dev vs learned oracle "
+          f"{dev_oracle:.2e}, vs plain {dev_plain:.2e}", flush=True)
+    # bfloat16 networks on both sides differ in accumulation order, so a few
+    # borderline cells can take different branches of the check
+    assert abs(fb - int(fbo.sum())) <= max(4, 0.02 * cells)
+    assert dev_oracle <= 1e-3
+
+
+def test_gain_report_polytrope(torch, trained):
+    import time
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: learned vs plain on the batched 4096-leaf polytrope", flush=True)
+    w = rotating_polytrope()
+    off = uneven_batches(w.n)
+    res = {}
+    for name, learned_on in (("plain", False), ("learned", True)):
+        hy = Hydro(max_leaves=w.n, schedule="auto", learned=learned_on)
+        try:
+            if learned_on:
+                hy.mlp_load(trained)
+            g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+            hy.step(g, 1e-3)
+            g.U.copy_(torch.tensor(w.U, device="cuda"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hy.step(g, 1e-3)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            stats = hy.mlp_stats() if learned_on else (0, 0)
+            res[name] = (w.cells * 2 / el, g.U.cpu().numpy(), stats)
+        finally:
+            hy.close()
+    rate_p, Up, _ = res["plain"]
+    rate_l, Ul, (cells, fb) = res["learned"]
+    l1 = np.abs(Ul - Up).sum() / np.abs(Up).sum()
+    print(f"plain {rate_p:.3e} cell-updates/s, learned {rate_l:.3e} (x{rate_l / rate_p:.2f}); "
+          f"fallback {fb}/{cells}; L1 rel deviation {l1:.2e}", flush=True)
+    assert np.isfinite(Ul).all() and l1 < 1e-2
