@@ -99,8 +99,9 @@ def test_uneven_batches_all_schedules_bitwise(torch):
         hy = Hydro(max_leaves=w.n, schedule=sched)
         try:
             g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
-            am = hy.step(g, 1e-3)
-            am2 = hy.step(g, 1e-3)
+            dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
+            am = hy.step(g, dt)
+            am2 = hy.step(g, float(w.cfl * np.min(w.tree.dx / am)))
             outs.append((g.U.cpu().numpy(), am, am2))
         finally:
             hy.close()
@@ -131,8 +132,9 @@ def test_autotune_table_and_cache(torch, tmp_path):
     try:
         ga = hy2.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
         gb = ref.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
-        hy2.step(ga, 1e-4)
-        ref.step(gb, 1e-4)
+        dt = float(w.cfl * np.min(w.tree.dx / ref.signal_speed(gb).cpu().numpy()))
+        hy2.step(ga, dt)
+        ref.step(gb, dt)
         assert np.all(_err(ga.U.cpu().numpy(), gb.U.cpu().numpy()) <= TOL)
     finally:
         hy2.close()

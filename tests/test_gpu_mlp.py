@@ -220,11 +220,12 @@ def test_gain_report_polytrope(torch, trained):
             if learned_on:
                 hy.mlp_load(trained)
             g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
-            hy.step(g, 1e-3)
+            dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
+            hy.step(g, dt)
             g.U.copy_(torch.tensor(w.U, device="cuda"))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            hy.step(g, 1e-3)
+            hy.step(g, dt)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             stats = hy.mlp_stats() if learned_on else (0, 0)
