@@ -68,7 +68,7 @@ typedef struct hydro_params {
     const char *tune_cache; /* NULL, or a JSON table written by hydro_autotune: loaded
                                at creation and used by HYDRO_SCHED_AUTO            */
     int32_t mlp_batch;  /* rows of the network's training workspace (0: 4096)     */
-    int32_t reserved;
+    int32_t rk_order;   /* SSP Runge-Kutta stages per step: 2 (default, 0 = 2) or 3 */
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */
@@ -111,9 +111,12 @@ int hydro_destroy(hydro_t *h);
  * the box.  Synchronous; needs no handle and no GPU. */
 int hydro_ghost_map(const hydro_tree *t, int32_t *map);
 
-/* One full two-stage SSP-RK2 step of all leaves, in place on g->U:
- *   U1 = U + dt L(U);  U <- (U + (U1 + dt L(U1))) / 2, then the tracer resync,
- * ghosts refreshed from the stage input before each stage (section IV-B).
+/* One full SSP Runge-Kutta step of all leaves, in place on g->U (Shu-Osher
+ * form, ghosts refreshed from the stage input before each stage, tracer
+ * resync after the last stage; section IV-B, three stages in section V-A2):
+ *   order 2: U1 = U + dt L(U);  U <- U/2 + (U1 + dt L(U1))/2
+ *   order 3: U1 = U + dt L(U);  U2 = 3U/4 + (U1 + dt L(U1))/4;
+ *            U <- U/3 + 2(U2 + dt L(U2))/3.
  * If amax_out (host, [g->n]) is non-NULL the call synchronises the stream,
  * writes each leaf's maximum signal speed over both stages and reports
  * HYDRO_ENONPHYS if a stage produced rho <= 0 or a non-finite value.  Otherwise
@@ -122,10 +125,11 @@ int hydro_ghost_map(const hydro_tree *t, int32_t *map);
 int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out);
 
 /* One stage with explicit buffers (device, [n][7][512] each; Uin provides the
- * ghosts of every leaf).  stage 1: Uout = Uin + dt L(Uin).  stage 2:
- * Uout = (Un + (Uin + dt L(Uin)))/2 and the tracer resync.  Uout may alias Un,
- * not Uin.  amax (device [n], may be NULL) receives each leaf's maximum
- * signal speed.  g->U is not used. */
+ * ghosts of every leaf).  stage 1: Uout = Uin + dt L(Uin); stage s > 1 of the
+ * handle's order: Uout = a Un + b (Uin + dt L(Uin)) with the coefficients
+ * above, and the tracer resync after the last stage.  Uout may alias Un, not
+ * Uin.  amax (device [n], may be NULL) receives each leaf's maximum signal
+ * speed.  g->U is not used. */
 int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
                 const double *Un, double *Uout, double *amax);
 

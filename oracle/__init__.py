@@ -63,6 +63,8 @@ def lib():
         L.oracle_leaf_rhs.argtypes = [dp, C.c_double, dp, C.POINTER(Phys), dp, dp]
         L.oracle_stage.argtypes = [C.c_void_p, C.c_int, C.c_double, dp, dp, dp, dp,
                                    C.POINTER(Phys), C.c_int, C.c_int, dp, dp]
+        L.oracle_stage_rk.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, dp, dp, dp, dp,
+                                      C.POINTER(Phys), C.c_int, C.c_int, dp, dp]
         L.oracle_signal_speed.argtypes = [C.c_void_p, dp, dp, dp, C.POINTER(Phys),
                                           C.c_int, C.c_int, dp]
         L.oracle_reconstruct.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
@@ -178,11 +180,31 @@ class Oracle:
         l1 = self.n if l1 is None else l1
         return Uout[l0:l1], amax[l0:l1]
 
-    def step(self, dt: float, U):
-        """Full SSP-RK2 step; returns (U_next, amax per leaf over both stages)."""
-        U1, a1 = self.stage(1, dt, U)
-        U2, a2 = self.stage(2, dt, U1, U)
-        return U2, np.maximum(a1, a2)
+    def step(self, dt: float, U, order: int = 2):
+        """Full SSP-RK step of order 2 or 3; returns (U_next, amax per leaf
+        over all stages)."""
+        if order == 2:
+            U1, a1 = self.stage(1, dt, U)
+            U2, a2 = self.stage(2, dt, U1, U)
+            return U2, np.maximum(a1, a2)
+        Un = _f64(U)
+        cur, amax = Un, np.zeros(self.n)
+        for s in range(1, order + 1):
+            cur, a = self.stage_rk(order, s, dt, cur, Un)
+            amax = np.maximum(amax, a)
+        return cur, amax
+
+    def stage_rk(self, order: int, stage: int, dt: float, Uin, Un):
+        Uin, Un = _f64(Uin), _f64(Un)
+        Uout = np.zeros_like(Uin)
+        amax = np.zeros(self.n)
+        L = lib()
+
+        def fn(a, b):
+            return L.oracle_stage_rk(self._t, order, stage, float(dt), _p(Uin), _p(Un), _p(self.dx),
+                                     _p(self.origin), C.byref(self.phys), a, b, _p(Uout), _p(amax))
+        self._run(fn, self._ranges())
+        return Uout, amax
 
     def signal_speed(self, U, l0=0, l1=None):
         U = _f64(U)

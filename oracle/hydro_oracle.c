@@ -426,11 +426,30 @@ static void resync(double *u[7], const oracle_phys *ph)
     if (eint > ph->eta2 * E) *u[5] = pow(eint, 1.0 / ph->gamma);
 }
 
+/* Shu-Osher coefficients of stage s (1-based) of the SSP Runge-Kutta
+ * integrator of the given order: Uout = a Un + b (Uin + dt L(Uin)). */
+static int ssp_coeffs(int order, int stage, double *a, double *b)
+{
+    if (order == 2 && stage == 2) { *a = 0.5; *b = 0.5; return 0; }
+    if (order == 3 && stage == 2) { *a = 0.75; *b = 0.25; return 0; }
+    if (order == 3 && stage == 3) { *a = 1.0 / 3.0; *b = 2.0 / 3.0; return 0; }
+    if (stage == 1 && (order == 2 || order == 3)) { *a = 0.0; *b = 1.0; return 0; }
+    return -2;
+}
+
 int oracle_stage(const void *t, int stage, double dt, const double *Uin, const double *Un,
                  const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
                  double *Uout, double *amax)
 {
-    if (stage != 1 && stage != 2) return -2;
+    return oracle_stage_rk(t, 2, stage, dt, Uin, Un, dx, origin, ph, l0, l1, Uout, amax);
+}
+
+int oracle_stage_rk(const void *t, int order, int stage, double dt, const double *Uin, const double *Un,
+                    const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
+                    double *Uout, double *amax)
+{
+    double ca, cb;
+    if (ssp_coeffs(order, stage, &ca, &cb)) return -2;
     double *P = (double *)malloc(sizeof(double) * NFLD * NPAD);
     double *dU = (double *)malloc(sizeof(double) * NFLD * NCELL);
     int rc = 0;
@@ -444,9 +463,9 @@ int oracle_stage(const void *t, int stage, double dt, const double *Uin, const d
             if (stage == 1)
                 Uout[base + e] = u + dt * dU[e];
             else
-                Uout[base + e] = 0.5 * (Un[base + e] + (u + dt * dU[e]));
+                Uout[base + e] = ca * Un[base + e] + cb * (u + dt * dU[e]);
         }
-        if (stage == 2)
+        if (stage == order)
             for (long c = 0; c < NCELL; ++c) {
                 double *u[7];
                 for (int f = 0; f < NFLD; ++f) u[f] = Uout + base + (long)f * NCELL + c;

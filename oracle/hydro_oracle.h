@@ -78,6 +78,14 @@ int oracle_stage(const void *t, int stage, double dt, const double *Uin, const d
                  const double *dx, const double *origin, const oracle_phys *ph,
                  int l0, int l1, double *Uout, double *amax);
 
+/* Stage `stage` of the SSP Runge-Kutta integrator of order 2 or 3 (Shu-Osher
+ * form): stage 1 as above; later stages Uout = a Un + b (Uin + dt L(Uin)) with
+ * (a, b) = (1/2, 1/2) for order 2, (3/4, 1/4) then (1/3, 2/3) for order 3; the
+ * tracer resync follows the last stage. */
+int oracle_stage_rk(const void *t, int order, int stage, double dt, const double *Uin, const double *Un,
+                    const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
+                    double *Uout, double *amax);
+
 /* Maximum signal speed of every leaf in [l0, l1) for the state U. */
 int oracle_signal_speed(const void *t, const double *U, const double *dx, const double *origin,
                         const oracle_phys *ph, int l0, int l1, double *amax);

@@ -22,6 +22,8 @@ struct hydro_t {
     hydro_params p;
     int device;
     double *U1 = nullptr;      // first-stage state [max_leaves][7][512]
+    double *U2 = nullptr;      // second-stage state of three-stage steps
+    int rk = 2;
     double *dscr = nullptr;    // column walk: [max_leaves][3][7][512]
     int *queue = nullptr;      // persistent launches: [2]
     int *leaf_done = nullptr;  // [max_leaves]
@@ -184,6 +186,13 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.dt = dt;
     a.stage = stage;
     a.amax_accumulate = accumulate;
+    a.last = stage == h->rk;
+    a.ca = 0.0;
+    a.cb = 1.0;
+    if (stage >= 2) {
+        a.ca = h->rk == 2 ? 0.5 : (stage == 2 ? 0.75 : 1.0 / 3.0);
+        a.cb = h->rk == 2 ? 0.5 : (stage == 2 ? 0.25 : 2.0 / 3.0);
+    }
     a.dscr = h->dscr;
     a.dt_dev = dt_dev;
     a.queue = h->queue;
@@ -288,11 +297,19 @@ int save_table(hydro_t *h, const char *path) {
     return f.good() ? HYDRO_OK : fail(h, HYDRO_EINVAL, "tune cache write failed");
 }
 
-// Stage 1, stage 2 and the next dt, all on the device.
+// All stages of one step, in place on g->U; per-leaf speeds accumulate in h->amax.
+int run_stages(hydro_t *h, const hydro_grid *g, double dt, const double *dt_dev, bool allow_timing) {
+    int rc;
+    if ((rc = run_stage(h, g, 1, dt, g->U, g->U, h->U1, h->amax, 0, dt_dev, allow_timing))) return rc;
+    if (h->rk == 2) return run_stage(h, g, 2, dt, h->U1, g->U, g->U, h->amax, 1, dt_dev, allow_timing);
+    if ((rc = run_stage(h, g, 2, dt, h->U1, g->U, h->U2, h->amax, 1, dt_dev, allow_timing))) return rc;
+    return run_stage(h, g, 3, dt, h->U2, g->U, g->U, h->amax, 1, dt_dev, allow_timing);
+}
+
+// All stages and the next dt, on the device.
 int run_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, bool allow_timing) {
     int rc;
-    if ((rc = run_stage(h, g, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, dt_dev, allow_timing))) return rc;
-    if ((rc = run_stage(h, g, 2, 0.0, h->U1, g->U, g->U, h->amax, 1, dt_dev, allow_timing))) return rc;
+    if ((rc = run_stages(h, g, 0.0, dt_dev, allow_timing))) return rc;
     hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
 }
@@ -363,6 +380,8 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (p->max_leaves <= 0) return fail(nullptr, HYDRO_EINVAL, "max_leaves must be > 0");
     if (p->recon != 0 && p->recon != 1) return fail(nullptr, HYDRO_EINVAL, "recon must be 0 or 1");
     if (p->mlp_batch < 0) return fail(nullptr, HYDRO_EINVAL, "mlp_batch must be >= 0");
+    if (p->rk_order != 0 && p->rk_order != 2 && p->rk_order != 3)
+        return fail(nullptr, HYDRO_EINVAL, "rk_order must be 2 or 3");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
         return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
@@ -370,6 +389,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (!h) return fail(nullptr, HYDRO_ENOMEM, "handle allocation");
     h->p = *p;
     h->device = p->device;
+    h->rk = p->rk_order == 3 ? 3 : 2;
     int rc = set_device(h);
     if (rc) { g_create_err = h->err; delete h; return rc; }
     hipError_t e = ensure_ghost_table(h->device);
@@ -388,6 +408,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     }
     const size_t n = (size_t)p->max_leaves;
     e = hipMalloc((void **)&h->U1, n * LEAF_STRIDE * sizeof(double));
+    if (e == hipSuccess && h->rk == 3) e = hipMalloc((void **)&h->U2, n * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->dscr, n * 3 * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->amax, n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * sizeof(int));
@@ -416,6 +437,7 @@ int hydro_destroy(hydro_t *h) {
     (void)hipSetDevice(h->device);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->U1) (void)hipFree(h->U1);
+    if (h->U2) (void)hipFree(h->U2);
     if (h->amax) (void)hipFree(h->amax);
     if (h->dscr) (void)hipFree(h->dscr);
     if (h->queue) (void)hipFree(h->queue);
@@ -435,8 +457,7 @@ int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out) {
     if (!g->U || !aligned8(g->U)) return fail(h, HYDRO_EINVAL, "U is NULL or misaligned");
     if (!(dt >= 0.0) || !isfinite(dt)) return fail(h, HYDRO_EINVAL, "dt must be finite and >= 0");
     if ((rc = set_device(h))) return rc;
-    if ((rc = run_stage(h, g, 1, dt, g->U, g->U, h->U1, h->amax, 0))) return rc;
-    if ((rc = run_stage(h, g, 2, dt, h->U1, g->U, g->U, h->amax, 1))) return rc;
+    if ((rc = run_stages(h, g, dt, nullptr, true))) return rc;
     if (amax_out) {
         hipStream_t s = (hipStream_t)g->stream;
         hipError_t e = hipMemcpyAsync(amax_out, h->amax, sizeof(double) * g->n, hipMemcpyDeviceToHost, s);
@@ -450,14 +471,14 @@ int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const dou
                 const double *Un, double *Uout, double *amax) {
     int rc = check_grid(h, g);
     if (rc) return rc;
-    if (stage != 1 && stage != 2) return fail(h, HYDRO_EINVAL, "stage must be 1 or 2");
-    if (!Uin || !Uout || (stage == 2 && !Un)) return fail(h, HYDRO_EINVAL, "null stage buffer");
+    if (stage < 1 || stage > h->rk) return fail(h, HYDRO_EINVAL, "stage must be 1.." + std::to_string(h->rk));
+    if (!Uin || !Uout || (stage >= 2 && !Un)) return fail(h, HYDRO_EINVAL, "null stage buffer");
     if (!aligned8(Uin) || !aligned8(Uout) || (Un && !aligned8(Un)))
         return fail(h, HYDRO_EINVAL, "stage buffers must be 8-byte aligned");
     if (Uin == Uout) return fail(h, HYDRO_EINVAL, "Uout may not alias Uin");
     if (!(dt >= 0.0) || !isfinite(dt)) return fail(h, HYDRO_EINVAL, "dt must be finite and >= 0");
     if ((rc = set_device(h))) return rc;
-    return run_stage(h, g, stage, dt, Uin, stage == 2 ? Un : Uin, Uout, amax, 0);
+    return run_stage(h, g, stage, dt, Uin, stage >= 2 ? Un : Uin, Uout, amax, 0);
 }
 
 int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax) {

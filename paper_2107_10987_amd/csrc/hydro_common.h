@@ -47,7 +47,9 @@ struct StageArgs {
     double dt;
     int leaf0;                // first leaf of this launch
     int nleaf;                // leaves in this launch
-    int stage;                // 1, 2; 0 = signal speed only
+    int stage;                // 1, 2, 3; 0 = signal speed only
+    int last;                 // last stage of the step: tracer resync
+    double ca, cb;            // stage > 1: Uout = ca Un + cb (Uin + dt L)
     int amax_accumulate;      // stage 2 of a step: amax = max(amax, this stage)
     int kernel;               // KERNEL_* below
     double *dscr;             // column walk: [n][3][7][512] per-axis flux differences

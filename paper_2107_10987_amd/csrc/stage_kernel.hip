@@ -247,7 +247,9 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
         for (int f = 0; f < NF; ++f) o[f] = u[f] + dt * L[f];
     } else {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) o[f] = 0.5 * (a.Un[base + (size_t)f * NC] + (u[f] + dt * L[f]));
+        for (int f = 0; f < NF; ++f) o[f] = a.ca * a.Un[base + (size_t)f * NC] + a.cb * (u[f] + dt * L[f]);
+    }
+    if (a.last) {
         // dual-energy resync of the tracer after the full step
         const double rinv = 1.0 / o[RHO];
         const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;

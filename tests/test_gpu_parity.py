@@ -221,3 +221,26 @@ def test_nonphysical_state_reported(hy, torch):
     # the flag is cleared: a good state steps cleanly afterwards
     g2 = _grid(hy, torch, w)
     hy.step(g2, 1e-3)
+
+
+@pytest.mark.parametrize("schedule", ["column", "tiled"])
+def test_rk3_steps_match_oracle(torch, schedule):
+    # three-stage SSP-RK (the paper's integrator) on the 32^3 Sedov blast
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: SSP-RK3, sedov-32^3, {schedule}", flush=True)
+    w = sedov_uniform(4)
+    o = _oracle(w)
+    hy = Hydro(max_leaves=w.n, schedule=schedule, rk_order=3)
+    try:
+        g = _grid(hy, torch, w)
+        U = w.U.copy()
+        dt = o.dt(U)
+        for s in range(3):
+            amax = hy.step(g, dt)
+            U, am = o.step(dt, U, order=3)
+            err = field_err(g.U.cpu().numpy(), U)
+            assert np.all(err <= TOL), (s, err)
+            assert np.abs(amax - am).max() <= TOL * am.max()
+            dt = float(w.cfl * np.min(w.tree.dx / am))
+    finally:
+        hy.close()

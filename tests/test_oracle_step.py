@@ -237,3 +237,53 @@ def test_3d_oracle_sod_against_exact():
     exact = er.cell_average(x - 0.5 / n, x + 0.5 / n, t_end, 0.5, (1.0, 0.0, 1.0),
                             (0.125, 0.0, 0.1), gamma)
     assert np.mean(np.abs(rho - exact)) < 1.2e-2
+
+
+def test_rk3_rotating_source_closed_form(oracle_mod):
+    # three-stage SSP-RK on ds/dt = A s gives the third-order Taylor polynomial
+    t = uniform_tree((2, 2, 1), (PERIODIC,) * 3, (0.0, 0.0, 0.0), 1.0 / 16)
+    U = _uniform_U(t, 1.0, (0.4, -0.3, 0.1), 1.0)
+    om, h = 0.9, 0.01
+    o = oracle_mod.Oracle(t, G, omega=om)
+    U1, _ = o.step(h, U, order=3)
+    A = om * np.array([[0.0, 1.0], [-1.0, 0.0]])
+    M = np.eye(2) + h * A + 0.5 * h * h * A @ A + h ** 3 / 6.0 * A @ A @ A
+    s1 = M @ np.array([U[0, 1, 0, 0, 0], U[0, 2, 0, 0, 0]])
+    assert np.allclose(U1[:, 1], s1[0], rtol=1e-15, atol=1e-16)
+    assert np.allclose(U1[:, 2], s1[1], rtol=1e-15, atol=1e-16)
+    # the (3/4, 1/4) and (1/3, 2/3) combinations of equal values round by an ulp
+    for f in (0, 3, 4, 6):
+        assert np.allclose(U1[:, f], U[:, f], rtol=4e-16, atol=0), f
+
+
+def test_rk3_conserves_and_rk2_stage_form_is_unchanged(oracle_mod):
+    w = blast_single_leaf()
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    dt = o.dt(w.U)
+    U3, _ = o.step(dt, w.U, order=3)
+    for f in (0, 4, 6):
+        assert abs(U3[:, f].sum() - w.U[:, f].sum()) <= 1e-14 * np.abs(w.U[:, f]).sum()
+    # the general stage form with (1/2, 1/2) is the two-stage step bit for bit
+    U1, _ = o.stage_rk(2, 1, dt, w.U, w.U)
+    U2, _ = o.stage_rk(2, 2, dt, U1, w.U)
+    assert np.array_equal(U2, o.step(dt, w.U)[0])
+
+
+def test_rk3_converges_at_third_order_in_time():
+    # time-refinement study of the rotating source (fluxes cancel exactly):
+    # the error against exp(tA) falls by ~8x when dt halves
+    import oracle
+    t = uniform_tree((1, 1, 1), (PERIODIC,) * 3, (0.0, 0.0, 0.0), 1.0 / 8)
+    U = _uniform_U(t, 1.0, (0.4, -0.3, 0.0), 1.0)
+    om, T = 2.0, 0.5
+    o = oracle.Oracle(t, G, omega=om)
+    s0 = np.array([U[0, 1, 0, 0, 0], U[0, 2, 0, 0, 0]])
+    c, s_ = np.cos(om * T), np.sin(om * T)
+    exact = np.array([[c, s_], [-s_, c]]) @ s0
+    errs = []
+    for n in (8, 16, 32):
+        V = U.copy()
+        for _ in range(n):
+            V, _ = o.step(T / n, V, order=3)
+        errs.append(np.hypot(V[0, 1, 0, 0, 0] - exact[0], V[0, 2, 0, 0, 0] - exact[1]))
+    assert 6.0 < errs[0] / errs[1] < 10.0 and 6.0 < errs[1] / errs[2] < 10.0
