@@ -69,6 +69,10 @@ typedef struct hydro_params {
                                at creation and used by HYDRO_SCHED_AUTO            */
     int32_t mlp_batch;  /* rows of the network's training workspace (0: 4096)     */
     int32_t rk_order;   /* SSP Runge-Kutta stages per step: 2 (default, 0 = 2) or 3 */
+    int32_t scheme;     /* 0: fluxes at the 9 points of every face (new scheme);
+                           1: at face centres only, weight 1 (the paper's old scheme,
+                           section IV-B); same reconstruction                      */
+    int32_t reserved;
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */

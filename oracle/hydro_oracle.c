@@ -348,8 +348,11 @@ double oracle_leaf_fluxes_from_values(const double *V, double dx, const double o
                     double xB[3];
                     for (int a = 0; a < 3; ++a) xB[a] = origin[a] + (double)B[a] * dx;
                     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-                    for (int a = -1; a <= 1; ++a)
-                        for (int b = -1; b <= 1; ++b) {
+                    /* the old scheme (section IV-B, last sentence) evaluates the
+                     * flux at the face centre only, with weight one */
+                    const int span = ph->centre_only ? 0 : 1;
+                    for (int a = -span; a <= span; ++a)
+                        for (int b = -span; b <= span; ++b) {
                             int dB[3], dA[3];
                             dB[n] = -1;
                             dB[t1] = a;
@@ -363,7 +366,8 @@ double oracle_leaf_fluxes_from_values(const double *V, double dx, const double o
                             for (int c = 0; c < 3; ++c) xq[c] = xB[c] + 0.5 * (double)dB[c] * dx;
                             double s = oracle_point_flux(n, UL, UR, xq, ph, F);
                             if (s > smax) smax = s;
-                            for (int f = 0; f < NFLD; ++f) acc[f] = acc[f] + SIMPSON[a + 1][b + 1] * F[f];
+                            const double w = ph->centre_only ? 1.0 : SIMPSON[a + 1][b + 1];
+                            for (int f = 0; f < NFLD; ++f) acc[f] = acc[f] + w * F[f];
                         }
                     double *dst = Fn + ((((long)n * 9 + fi) * NX + c1) * NX + c2) * NFLD;
                     for (int f = 0; f < NFLD; ++f) dst[f] = acc[f];

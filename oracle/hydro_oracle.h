@@ -25,6 +25,7 @@ typedef struct {
     double omega;   /* frame rotation rate about the z axis through x = y = 0 */
     double eta1;    /* dual-energy pressure switch at face points */
     double eta2;    /* dual-energy tracer resync threshold after a step */
+    int centre_only; /* 1: the old scheme, one flux point at each face centre */
 } oracle_phys;
 
 /* One-dimensional PPM on five equally spaced values q[0..4] = q_{-2..2}:

@@ -202,6 +202,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.mlp_y = nullptr;
     a.mlp_sigma = nullptr;
     a.mlp_ok = nullptr;
+    a.centre_only = h->p.scheme == 1;
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
@@ -382,6 +383,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (p->mlp_batch < 0) return fail(nullptr, HYDRO_EINVAL, "mlp_batch must be >= 0");
     if (p->rk_order != 0 && p->rk_order != 2 && p->rk_order != 3)
         return fail(nullptr, HYDRO_EINVAL, "rk_order must be 2 or 3");
+    if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, HYDRO_EINVAL, "scheme must be 0 or 1");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
         return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");

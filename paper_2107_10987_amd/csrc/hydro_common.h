@@ -50,6 +50,7 @@ struct StageArgs {
     int stage;                // 1, 2, 3; 0 = signal speed only
     int last;                 // last stage of the step: tracer resync
     double ca, cb;            // stage > 1: Uout = ca Un + cb (Uin + dt L)
+    int centre_only;          // old scheme: one flux point per face, weight 1
     int amax_accumulate;      // stage 2 of a step: amax = max(amax, this stage)
     int kernel;               // KERNEL_* below
     double *dscr;             // column walk: [n][3][7][512] per-axis flux differences

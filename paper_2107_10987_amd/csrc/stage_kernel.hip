@@ -132,7 +132,8 @@ __device__ __forceinline__ double side_flux(const double U[NF], double xq, doubl
 // Simpson-weighted flux through the face of axis N owned by this thread.
 template <int N>
 __device__ __forceinline__ void face_flux(const double *P, int r, double dx, const double org[3],
-                                          const Phys &ph, double acc[NF], double &smax) {
+                                          const Phys &ph, bool centre_only, double acc[NF],
+                                          double &smax) {
     constexpr int T1 = (N == 0) ? 1 : 0;
     constexpr int T2 = (N == 2) ? 1 : 2;
     constexpr int E0 = (N == 0) ? NX + 1 : NX;
@@ -150,9 +151,10 @@ __device__ __forceinline__ void face_flux(const double *P, int r, double dx, con
     for (int f = 0; f < NF; ++f) acc[f] = 0.0;
     const double wts[3] = {1.0 / 36.0, 4.0 / 36.0, 1.0 / 36.0};
     const double wc[3] = {4.0 / 36.0, 16.0 / 36.0, 4.0 / 36.0};
-    for (int a = -1; a <= 1; ++a) {
+    const int span = centre_only ? 0 : 1;
+    for (int a = -span; a <= span; ++a) {
 #pragma unroll 1
-        for (int b = -1; b <= 1; ++b) {
+        for (int b = -span; b <= span; ++b) {
             int dA[3], dB[3];
             dA[N] = 1;
             dB[N] = -1;
@@ -169,7 +171,7 @@ __device__ __forceinline__ void face_flux(const double *P, int r, double dx, con
             const double sr = side_flux<N>(UR, xq, yq, ph, FR);
             const double s = sl > sr ? sl : sr;
             smax = s > smax ? s : smax;
-            const double w = (a == 0) ? wc[b + 1] : wts[b + 1];
+            const double w = centre_only ? 1.0 : ((a == 0) ? wc[b + 1] : wts[b + 1]);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const double Fq = 0.5 * (FL[f] + FR[f]) - 0.5 * s * (UR[f] - UL[f]);
@@ -302,9 +304,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     const double org[3] = {a.origin[3 * leaf], a.origin[3 * leaf + 1], a.origin[3 * leaf + 2]};
     double F0[NF], F1[NF], F2[NF];
     double smax = 0.0;
-    face_flux<0>(P, tid, dx, org, a.ph, F0, smax);
-    face_flux<1>(P, tid, dx, org, a.ph, F1, smax);
-    face_flux<2>(P, tid, dx, org, a.ph, F2, smax);
+    face_flux<0>(P, tid, dx, org, a.ph, a.centre_only, F0, smax);
+    face_flux<1>(P, tid, dx, org, a.ph, a.centre_only, F1, smax);
+    face_flux<2>(P, tid, dx, org, a.ph, a.centre_only, F2, smax);
     __syncthreads();  // the input block is dead from here on
 
     double *Fl = P;                      // [f][axis][576]
@@ -469,19 +471,21 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
 #pragma unroll
         for (int f = 0; f < NF; ++f) prev[f] = shfl_up1(pos[f]);
         if (face) {
-            const double s = point_flux_acc<N>(prev, neg, qx(0, 0), qy(0, 0), ph, 16.0 / 36.0, acc);
+            const double w0 = a.centre_only ? 1.0 : 16.0 / 36.0;
+            const double s = point_flux_acc<N>(prev, neg, qx(0, 0), qy(0, 0), ph, w0, acc);
             smax = s > smax ? s : smax;
         }
     }
     // line pairs {(a,b), (-a,-b)} for (a,b) = (1,0), (0,1), (1,1), (1,-1)
+    const int npairs = a.centre_only ? 0 : 4;
 #pragma unroll 1
-    for (int p = 0; p < 4; ++p) {
-        const int a = (p == 1) ? 0 : 1;
-        const int b = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
+    for (int p = 0; p < npairs; ++p) {
+        const int ta = (p == 1) ? 0 : 1;
+        const int tb = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
         const double w = (p < 2) ? 4.0 / 36.0 : 1.0 / 36.0;
         double pos1[NF], neg1[NF], pos2[NF], neg2[NF];
-        line_vals(P, cB, dirx(a, b), diry(a, b), dirz(a, b), src, pos1, neg1);
-        line_vals(P, cB, dirx(-a, -b), diry(-a, -b), dirz(-a, -b), src, pos2, neg2);
+        line_vals(P, cB, dirx(ta, tb), diry(ta, tb), dirz(ta, tb), src, pos1, neg1);
+        line_vals(P, cB, dirx(-ta, -tb), diry(-ta, -tb), dirz(-ta, -tb), src, pos2, neg2);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             pos1[f] = shfl_up1(pos1[f]);
@@ -489,10 +493,10 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
         }
         if (face) {
             // point (a,b): left = +end of line (a,b) below, right = -end of line (-a,-b) here
-            double s = point_flux_acc<N>(pos1, neg2, qx(a, b), qy(a, b), ph, w, acc);
+            double s = point_flux_acc<N>(pos1, neg2, qx(ta, tb), qy(ta, tb), ph, w, acc);
             smax = s > smax ? s : smax;
             // point (-a,-b): left = +end of line (-a,-b) below, right = -end of line (a,b) here
-            s = point_flux_acc<N>(pos2, neg1, qx(-a, -b), qy(-a, -b), ph, w, acc);
+            s = point_flux_acc<N>(pos2, neg1, qx(-ta, -tb), qy(-ta, -tb), ph, w, acc);
             smax = s > smax ? s : smax;
         }
     }

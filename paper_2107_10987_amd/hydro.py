@@ -36,7 +36,8 @@ class HydroError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
                 ("schedule", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
-                ("tune_cache", C.c_char_p), ("mlp_batch", C.c_int32), ("rk_order", C.c_int32)]
+                ("tune_cache", C.c_char_p), ("mlp_batch", C.c_int32), ("rk_order", C.c_int32),
+                ("scheme", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -128,7 +129,7 @@ class Hydro:
 
     def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
                  schedule: str = "auto", tune_cache: str | None = None, learned: bool = False,
-                 mlp_batch: int = 4096, rk_order: int = 2):
+                 mlp_batch: int = 4096, rk_order: int = 2, centre_only: bool = False):
         import torch
         self.torch = torch
         self.L = load()
@@ -137,7 +138,7 @@ class Hydro:
         self.learned = learned
         self.p = Params(int(max_leaves), int(device), int(bool(learned)), SCHEDULES[schedule],
                         float(eta1), float(eta2), tune_cache.encode() if tune_cache else None,
-                        int(mlp_batch), int(rk_order))
+                        int(mlp_batch), int(rk_order), int(bool(centre_only)), 0)
         h = C.c_void_p()
         rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
         if rc:

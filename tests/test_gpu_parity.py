@@ -244,3 +244,26 @@ def test_rk3_steps_match_oracle(torch, schedule):
             dt = float(w.cfl * np.min(w.tree.dx / am))
     finally:
         hy.close()
+
+
+@pytest.mark.parametrize("schedule", ["column", "face"])
+def test_old_scheme_matches_oracle(torch, schedule):
+    # the paper's old scheme: same reconstruction, flux at face centres only
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: face-centre scheme, sedov-32^3, {schedule}", flush=True)
+    w = sedov_uniform(4)
+    o = oracle.Oracle(w.tree, w.gamma, w.omega, centre_only=True)
+    hy = Hydro(max_leaves=w.n, schedule=schedule, centre_only=True)
+    try:
+        g = _grid(hy, torch, w)
+        U = w.U.copy()
+        dt = o.dt(U)
+        for s in range(3):
+            amax = hy.step(g, dt)
+            U, am = o.step(dt, U)
+            assert np.all(field_err(g.U.cpu().numpy(), U) <= TOL), s
+            assert np.abs(amax - am).max() <= TOL * am.max()
+            dt = float(w.cfl * np.min(w.tree.dx / am))
+    finally:
+        hy.close()
