@@ -173,15 +173,18 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
  * A 34-64-64-26 network (tanh-GELU) maps the normalised 3x3x3 neighbourhood of
  * a cell, x_k = (q_nb - q_c)/sigma with sigma = max |q_nb - q_c|, plus a
  * one-hot field id, to the 26 point values q_c + sigma*y_d.  It runs on
- * bfloat16 MFMA with FP32 accumulation; every value is checked in FP64
- * (between the cell and its neighbour in that direction, PPM monotonicity of
- * each line's pair, rho, E, tau > 0 and X >= 0) and a cell any of whose
- * fields fails takes plain PPM.  Fluxes, update and conservation stay FP64.
+ * bfloat16 MFMA with FP32 accumulation; the plain limiter then acts on the
+ * predicted values (clamp between the cell and its neighbour in that
+ * direction, PPM monotonicity constraint on each line's pair), every value is
+ * checked in FP64 (bounds, monotonicity, rho, E, tau > 0 and X >= 0) and a
+ * cell any of whose fields fails takes plain PPM.  Fluxes, update and
+ * conservation stay FP64.
  * Parameters: float32 vector of 8090 values, W1[64][34], b1[64], W2[64][64],
  * b2[64], W3[26][64], b3[26].  Not a method of the paper: an extension. */
 
 /* Set the network's parameters (host [8090]); resets the Adam state.
- * Synchronous. */
+ * Non-finite parameters are accepted: every row they touch fails the check
+ * and falls back to plain PPM.  Synchronous. */
 int hydro_mlp_load(hydro_t *h, const float *params);
 /* Copy the current float32 parameters to host params[8090]. Synchronous. */
 int hydro_mlp_save(hydro_t *h, float *params);

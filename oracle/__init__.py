@@ -78,6 +78,7 @@ def lib():
                                   C.c_double, C.c_int]
         L.oracle_mlp_features.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp]
         L.oracle_mlp_row_ok.argtypes = [dp, dp, C.c_int]
+        L.oracle_mlp_limit.argtypes = [dp, dp]
         L.oracle_learned_values.argtypes = [dp, fp, dp, ip, ip]
         L.oracle_reconstruct_values.argtypes = [dp, dp]
         L.oracle_stage_learned.argtypes = [C.c_void_p, fp, C.c_int, C.c_double, dp, dp, dp, dp,
@@ -340,6 +341,13 @@ def mlp_features(P, i, j, k, f):
 
 def mlp_row_ok(nb, vals, f) -> bool:
     return bool(lib().oracle_mlp_row_ok(_p(_f64(nb)), _p(_f64(vals)), int(f)))
+
+
+def mlp_limit(nb, vals):
+    """The plain limiter applied to one row of predicted values (copy)."""
+    v = _f64(vals).copy()
+    lib().oracle_mlp_limit(_p(_f64(nb)), _p(v))
+    return v
 
 
 def learned_values(P, params):

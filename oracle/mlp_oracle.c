@@ -6,7 +6,9 @@
  * sigma = max |q_nb - q_c|, and joined to a one-hot field id (34 inputs); two
  * hidden layers of 64 with tanh-GELU give 26 outputs y_d, and the point value
  * is q_c + sigma * y_d in FP64.  A flat neighbourhood (sigma = 0) passes q_c
- * through exactly.  Every row is checked in FP64: each value must lie
+ * through exactly.  The plain limiter then acts on the predicted values
+ * (clamp between the cell and each neighbour, PPM monotonicity constraint per
+ * line), and every row is checked in FP64: each value must lie
  * between the cell and its neighbour in that direction, each line's pair of
  * end values must satisfy the PPM monotonicity conditions, and rho, E, tau
  * must stay positive and X non-negative; a cell any of whose fields fails is
@@ -231,6 +233,40 @@ int oracle_mlp_row_ok(const double nb[27], const double val[26], int f)
     return 1;
 }
 
+/* The plain limiter applied to one row of predicted values: each value is
+ * clamped between the cell and its neighbour in that direction, then each
+ * line's pair goes through the PPM monotonicity constraint (flatten at an
+ * extremum, else pull the far end in).  Values that already satisfy both are
+ * left unchanged; a NaN stays NaN and fails the check afterwards. */
+void oracle_mlp_limit(const double nb[27], double val[26])
+{
+    double qc = nb[13];
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                double qn = nb[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)];
+                double lo = qc < qn ? qc : qn, hi = qc < qn ? qn : qc;
+                double *v = &val[d26(dx, dy, dz)];
+                if (*v < lo) *v = lo;
+                if (*v > hi) *v = hi;
+            }
+    for (int ln = 0; ln < 13; ++ln) {
+        const int *d = LINES[ln];
+        double *R = &val[d26(d[0], d[1], d[2])], *L = &val[d26(-d[0], -d[1], -d[2])];
+        if ((*R - qc) * (qc - *L) <= 0.0) {
+            *L = qc;
+            *R = qc;
+        } else {
+            double D = *R - *L, M6 = 6.0 * (qc - 0.5 * (*L + *R));
+            if (D * M6 > D * D)
+                *L = 3.0 * qc - 2.0 * *R;
+            else if (D * M6 < -(D * D))
+                *R = 3.0 * qc - 2.0 * *L;
+        }
+    }
+}
+
 /* Point-value table (oracle_reconstruct_values layout) of one padded block
  * by the learned reconstruction with plain-PPM fallback.  Cells needed by the
  * fluxes are the interior and the face-adjacent ghost cells; *needed and
@@ -255,6 +291,7 @@ void oracle_learned_values(const double *P, const float *par, double *V, int *ne
                     }
                     oracle_mlp_forward(par, 1, x, 1, y, NULL, NULL, NULL, NULL);
                     for (int d = 0; d < 26; ++d) vals[f][d] = nb[13] + s * y[d];
+                    oracle_mlp_limit(nb, vals[f]);
                     if (!oracle_mlp_row_ok(nb, vals[f], f)) ok = 0;
                 }
                 const long c = rix(i, j, k);

@@ -39,8 +39,7 @@ struct hydro_t {
     int mlp_batch = 0;
     int adam_t = 0;
     bool mlp_loaded = false;
-    float *mlp_y = nullptr;        // [max_leaves][896][7][26]
-    double *mlp_sigma = nullptr;   // [max_leaves][896][7]
+    double *mlp_val = nullptr;     // [max_leaves][896][7][26]
     uint8_t *mlp_ok = nullptr;     // [max_leaves][896]
     uint16_t *ghost_pad = nullptr; // [2232]
     unsigned long long *fb_count = nullptr;
@@ -199,8 +198,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.leaf_done = h->leaf_done;
     a.tile_amax = h->tile_amax;
     a.grid_limit = h->num_cu;
-    a.mlp_y = nullptr;
-    a.mlp_sigma = nullptr;
+    a.mlp_val = nullptr;
     a.mlp_ok = nullptr;
     a.centre_only = h->p.scheme == 1;
     hipStream_t s = (hipStream_t)g->stream;
@@ -219,16 +217,14 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.ghost_pad = h->ghost_pad;
             m.wb = h->mt.wb;
             m.par = h->mt.par;
-            m.y = h->mlp_y;
-            m.sigma = h->mlp_sigma;
+            m.val = h->mlp_val;
             m.cell_ok = h->mlp_ok;
             m.fb_count = h->fb_count;
             m.leaf0 = a.leaf0;
             hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, s);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
             h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
-            a.mlp_y = h->mlp_y;
-            a.mlp_sigma = h->mlp_sigma;
+            a.mlp_val = h->mlp_val;
             a.mlp_ok = h->mlp_ok;
             if (a.kernel == KERNEL_FACE) a.kernel = KERNEL_COLUMN;   // the face walk has no learned variant
         }
@@ -351,8 +347,7 @@ hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
     if (e == hipSuccess) e = mlp_alloc(h, &t.loss_rows, B);
     if (e == hipSuccess) e = mlp_alloc(h, &h->fb_count, 1);
     if (e == hipSuccess && h->p.recon == 1) {
-        e = mlp_alloc(h, &h->mlp_y, nleaves * mlp::NSLOT * NF * 26);
-        if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_sigma, nleaves * mlp::NSLOT * NF);
+        e = mlp_alloc(h, &h->mlp_val, nleaves * mlp::NSLOT * NF * 26);
         if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_ok, nleaves * mlp::NSLOT);
         if (e == hipSuccess) e = mlp_alloc(h, &h->ghost_pad, (size_t)NG);
         if (e == hipSuccess) {
@@ -605,8 +600,6 @@ int hydro_mlp_load(hydro_t *h, const float *params) {
     if (!params) return fail(h, HYDRO_EINVAL, "null params");
     int rc = set_device(h);
     if (rc) return rc;
-    for (int i = 0; i < mlp::NPAR; ++i)
-        if (!isfinite(params[i])) return fail(h, HYDRO_EINVAL, "non-finite parameter");
     hipError_t e = hipMemcpy(h->mt.par, params, sizeof(float) * mlp::NPAR, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(h->mt.m, 0, sizeof(float) * mlp::NPAR);
     if (e == hipSuccess) e = hipMemset(h->mt.v, 0, sizeof(float) * mlp::NPAR);

@@ -62,8 +62,7 @@ struct StageArgs {
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
     // learned reconstruction (null: plain PPM)
-    const float *mlp_y;       // [n][896][7][26]
-    const double *mlp_sigma;  // [n][896][7]
+    const double *mlp_val;    // [n][896][7][26] learned point values
     const uint8_t *mlp_ok;    // [n][896]
 };
 

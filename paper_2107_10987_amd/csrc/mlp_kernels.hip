@@ -305,6 +305,43 @@ __constant__ uint16_t c_slot_cell[NSLOT];   // needed cell slot -> 12^3 index of
 
 __device__ __forceinline__ int p12(int i, int j, int k) { return ((k + 2) * RB12 + (j + 2)) * RB12 + (i + 2); }
 
+// The plain limiter on one row of predicted values (same expressions as the
+// oracle's): clamp between the cell and each neighbour, then the PPM
+// monotonicity constraint on each line's pair.  NaN stays NaN.
+__device__ __forceinline__ void limit_row(const double nb[27], double val[26]) {
+    const double qc = nb[13];
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        if (o == 13) continue;
+        const int d = o < 13 ? o : o - 1;
+        const double qn = nb[o];
+        const double lo = qc < qn ? qc : qn, hi = qc < qn ? qn : qc;
+        double v = val[d];
+        v = (v < lo) ? lo : v;
+        v = (v > hi) ? hi : v;
+        val[d] = v;
+    }
+    const int lines[13] = {14, 16, 22, 17, 11, 23, 5, 25, 7, 26, 8, 20, 2};   // dir27 of +d
+#pragma unroll
+    for (int l = 0; l < 13; ++l) {
+        const int op = lines[l], om = 26 - op;
+        const int ip = op < 13 ? op : op - 1, im = om < 13 ? om : om - 1;
+        double R = val[ip], L = val[im];
+        if ((R - qc) * (qc - L) <= 0.0) {
+            L = qc;
+            R = qc;
+        } else {
+            const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
+            if (D * M6 > D * D)
+                L = 3.0 * qc - 2.0 * R;
+            else if (D * M6 < -(D * D))
+                R = 3.0 * qc - 2.0 * L;
+        }
+        val[ip] = R;
+        val[im] = L;
+    }
+}
+
 // FP64 acceptance test of one row (same expressions as the oracle's).
 __device__ __forceinline__ bool row_ok(const double nb[27], const double val[26], int f) {
     const double qc = nb[13];
@@ -336,8 +373,8 @@ __device__ __forceinline__ bool row_ok(const double nb[27], const double val[26]
 
 // One workgroup per leaf: stage cells -2..9 of every field in LDS, then each
 // wave takes chunks of 9 cells x 7 fields = 63 rows (lane = row): FP64
-// features, the network on MFMA, FP64 denormalisation and check.  Writes the
-// outputs y (FP32), sigma (FP64) and a per-cell pass flag.
+// features, the network on MFMA, FP64 denormalisation, the plain limiter and
+// the check.  Writes the FP64 point values and a per-cell pass flag.
 __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
     __shared__ double B12[NF * RB12 * RB12 * RB12];      // 96,768 B
     __shared__ uint16_t S[4][64 * 64];                   // 32,768 B
@@ -410,12 +447,9 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
         }
         forward64(s, m.wb, m.par, lane, nullptr, nullptr, nullptr, nullptr, 0, 0);
         double val[26];
-        float yv[26];
 #pragma unroll
-        for (int d = 0; d < 26; ++d) {
-            yv[d] = flat ? 0.f : ys[lane * 32 + d];
-            val[d] = flat ? qc : qc + sigma * (double)yv[d];
-        }
+        for (int d = 0; d < 26; ++d) val[d] = flat ? qc : qc + sigma * (double)ys[lane * 32 + d];
+        if (!flat) limit_row(nb, val);
         const bool ok = !live || flat || row_ok(nb, val, f);
         const unsigned long long mask = __ballot(ok);
         // count the cells that fall back to plain PPM (lane 7m holds cell m)
@@ -425,8 +459,7 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
         if (live) {
             const size_t row = ((size_t)leaf * NSLOT + slot) * NF + f;
 #pragma unroll
-            for (int d = 0; d < 26; ++d) m.y[row * 26 + d] = yv[d];
-            m.sigma[row] = flat ? 0.0 : sigma;
+            for (int d = 0; d < 26; ++d) m.val[row * 26 + d] = val[d];
             if (f == 0) {
                 const unsigned bits = (unsigned)((mask >> (7 * (lane / 7))) & 0x7fu);
                 m.cell_ok[(size_t)leaf * NSLOT + slot] = bits == 0x7fu ? 1 : 0;

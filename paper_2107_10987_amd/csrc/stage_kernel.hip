@@ -103,6 +103,33 @@ __device__ __forceinline__ void point_state(const double *P, int c, int dx, int 
     }
 }
 
+// Euler flux along axis n (run-time) of one reconstructed state; returns |u_n| + c.
+__device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double xq, double yq,
+                                               const Phys &ph, double F[NF]) {
+    const double rho = U[RHO], E = U[EGAS], tau = U[TAU];
+    const double rinv = 1.0 / rho;
+    const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
+    const double vn = (n == 0) ? v0 : ((n == 1) ? v1 : v2);
+    // velocity relative to the grid rotating about z: u = v - omega x r
+    const double ux = v0 + ph.omega * yq;
+    const double uy = v1 - ph.omega * xq;
+    const double un = (n == 0) ? ux : ((n == 1) ? uy : v2);
+    const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
+    double eint = E - ek;
+    if (eint < ph.eta1 * E) eint = pow(tau, ph.gamma);
+    const double p = (ph.gamma - 1.0) * eint;
+    const double cs = sqrt(ph.gamma * p * rinv);
+    F[RHO] = rho * un;
+    const double fx = U[SX] * un, fy = U[SY] * un, fz = U[SZ] * un;
+    F[SX] = (n == 0) ? fx + p : fx;
+    F[SY] = (n == 1) ? fy + p : fy;
+    F[SZ] = (n == 2) ? fz + p : fz;
+    F[EGAS] = E * un + p * vn;
+    F[TAU] = tau * un;
+    F[SPC] = U[SPC] * un;
+    return fabs(un) + cs;
+}
+
 // Euler flux along axis N of one reconstructed state; returns |u_N| + c.
 template <int N>
 __device__ __forceinline__ double side_flux(const double U[NF], double xq, double yq,
@@ -382,11 +409,9 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
 }
 
 // Where a lane's point values come from: plain PPM, or (learned
-// reconstruction, cell passed the FP64 check) q_c + sigma * y from the
-// inference pre-pass.
+// reconstruction, cell passed the FP64 check) the inference pre-pass.
 struct ValSrc {
-    const float *y;        // [7][26] of this cell, or null for plain PPM
-    const double *sigma;   // [7]
+    const double *val;     // [7][26] of this cell, or null for plain PPM
 };
 
 __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
@@ -396,13 +421,12 @@ __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
 
 __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy, int dz,
                                           const ValSrc &src, double pos[NF], double neg[NF]) {
-    if (src.y) {
+    if (src.val) {
         const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const double qc = P[f * NP + c], sg = src.sigma[f];
-            pos[f] = qc + sg * (double)src.y[f * 26 + dp];
-            neg[f] = qc + sg * (double)src.y[f * 26 + dm];
+            pos[f] = src.val[f * 26 + dp];
+            neg[f] = src.val[f * 26 + dm];
         }
     } else {
         line_ends(P, c, dx, dy, dz, pos, neg);
@@ -412,15 +436,14 @@ __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy
 __device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double shfl_down1(double v) { return __shfl_down(v, 1, 64); }
 
-// Central-upwind flux at one face point of axis N, Simpson weight w added
+// Central-upwind flux at one face point of axis n, Simpson weight w added
 // into acc; returns the signal speed.
-template <int N>
-__device__ __forceinline__ double point_flux_acc(const double UL[NF], const double UR[NF],
+__device__ __forceinline__ double point_flux_acc(int n, const double UL[NF], const double UR[NF],
                                                  double xq, double yq, const Phys &ph, double w,
                                                  double acc[NF]) {
     double FL[NF], FR[NF];
-    const double sl = side_flux<N>(UL, xq, yq, ph, FL);
-    const double sr = side_flux<N>(UR, xq, yq, ph, FR);
+    const double sl = side_flux_rt(n, UL, xq, yq, ph, FL);
+    const double sr = side_flux_rt(n, UR, xq, yq, ph, FR);
     const double s = sl > sr ? sl : sr;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -430,10 +453,10 @@ __device__ __forceinline__ double point_flux_acc(const double UL[NF], const doub
     return s;
 }
 
-// Flux difference F(face above) - F(face below) along axis N of this lane's
-// cell, for column `col` and cell index `cell` in -1..8.
-template <int N>
-__device__ __forceinline__ void column_axis(const double *P, int col, int cell, double dx,
+// Flux difference F(face above) - F(face below) along axis N (run-time, so
+// one copy of the walk serves all three axes) of this lane's cell, for
+// column `col` and cell index `cell` in -1..8.
+__device__ __forceinline__ void column_axis(int N, const double *P, int col, int cell, double dx,
                                             double ox, double oy, double oz, const Phys &ph,
                                             const StageArgs &a, int leaf, double dsum[NF],
                                             double &smax) {
@@ -443,13 +466,10 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
     const int bj = (N == 1) ? cell : ((N == 0) ? c1 : c2);
     const int bk = (N == 2) ? cell : c2;
     const int cB = pidx(bi, bj, bk);
-    ValSrc src{nullptr, nullptr};
-    if (a.mlp_y) {
+    ValSrc src{nullptr};
+    if (a.mlp_val) {
         const size_t row = (size_t)leaf * mlp::NSLOT + mlp::slot_of(bi, bj, bk);
-        if (a.mlp_ok[row]) {
-            src.y = a.mlp_y + row * NF * 26;
-            src.sigma = a.mlp_sigma + row * NF;
-        }
+        if (a.mlp_ok[row]) src.val = a.mlp_val + row * NF * 26;
     }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;
@@ -459,9 +479,9 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = 0.0;
     // direction e_N + a t1 + b t2 in (x, y, z)
-    auto dirx = [](int a, int b) { return (N == 0) ? 1 : a; };
-    auto diry = [](int a, int b) { return (N == 1) ? 1 : ((N == 0) ? a : b); };
-    auto dirz = [](int a, int b) { return (N == 2) ? 1 : b; };
+    auto dirx = [N](int a, int b) { return (N == 0) ? 1 : a; };
+    auto diry = [N](int a, int b) { return (N == 1) ? 1 : ((N == 0) ? a : b); };
+    auto dirz = [N](int a, int b) { return (N == 2) ? 1 : b; };
     // point positions x(B) + d_B dx / 2, d_B = -e_N + a t1 + b t2
     auto qx = [&](int a, int b) { return xB + 0.5 * (double)((N == 0) ? -1 : a) * dx; };
     auto qy = [&](int a, int b) { return yB + 0.5 * (double)((N == 1) ? -1 : ((N == 0) ? a : b)) * dx; };
@@ -472,7 +492,7 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
         for (int f = 0; f < NF; ++f) prev[f] = shfl_up1(pos[f]);
         if (face) {
             const double w0 = a.centre_only ? 1.0 : 16.0 / 36.0;
-            const double s = point_flux_acc<N>(prev, neg, qx(0, 0), qy(0, 0), ph, w0, acc);
+            const double s = point_flux_acc(N, prev, neg, qx(0, 0), qy(0, 0), ph, w0, acc);
             smax = s > smax ? s : smax;
         }
     }
@@ -493,10 +513,10 @@ __device__ __forceinline__ void column_axis(const double *P, int col, int cell, 
         }
         if (face) {
             // point (a,b): left = +end of line (a,b) below, right = -end of line (-a,-b) here
-            double s = point_flux_acc<N>(pos1, neg2, qx(ta, tb), qy(ta, tb), ph, w, acc);
+            double s = point_flux_acc(N, pos1, neg2, qx(ta, tb), qy(ta, tb), ph, w, acc);
             smax = s > smax ? s : smax;
             // point (-a,-b): left = +end of line (-a,-b) below, right = -end of line (a,b) here
-            s = point_flux_acc<N>(pos2, neg1, qx(-ta, -tb), qy(-ta, -tb), ph, w, acc);
+            s = point_flux_acc(N, pos2, neg1, qx(-ta, -tb), qy(-ta, -tb), ph, w, acc);
             smax = s > smax ? s : smax;
         }
     }
@@ -524,14 +544,13 @@ struct ColLane {
 
 // Flux differences of one axis of one leaf into its workspace slice W
 // (linear cell index); returns this lane's signal speed maximum.
-template <int N>
-__device__ __forceinline__ void col_axis_to_ws(const StageArgs &a, const double *P, const ColLane &L,
-                                               int leaf, double *W, double &smax) {
+__device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const double *P,
+                                               const ColLane &L, int leaf, double *W, double &smax) {
     const double dx = a.dx[leaf];
     const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
     double d[NF];
     double sm = 0.0;
-    column_axis<N>(P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, d, sm);
+    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, d, sm);
     smax = L.live && sm > smax ? sm : smax;
     if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
         const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
@@ -568,9 +587,8 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     const ColLane L(tid);
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
     double smax = 0.0;
-    col_axis_to_ws<0>(a, P, L, leaf, W, smax);
-    col_axis_to_ws<1>(a, P, L, leaf, W, smax);
-    col_axis_to_ws<2>(a, P, L, leaf, W, smax);
+#pragma unroll 1
+    for (int n = 0; n < 3; ++n) col_axis_to_ws(n, a, P, L, leaf, W, smax);
     const double wm = wave_max(smax);
     __syncthreads();  // the input block is dead; workspace writes are visible
     double *red = P;
@@ -603,17 +621,9 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
-        if (T == 1) {
-            col_axis_to_ws<0>(a, P, L, leaf, W, smax);
-            col_axis_to_ws<1>(a, P, L, leaf, W, smax);
-            col_axis_to_ws<2>(a, P, L, leaf, W, smax);
-        } else if (tile == 0) {
-            col_axis_to_ws<0>(a, P, L, leaf, W, smax);
-        } else if (tile == 1) {
-            col_axis_to_ws<1>(a, P, L, leaf, W, smax);
-        } else {
-            col_axis_to_ws<2>(a, P, L, leaf, W, smax);
-        }
+        const int n0 = T == 1 ? 0 : tile, n1 = T == 1 ? 3 : tile + 1;
+#pragma unroll 1
+        for (int n = n0; n < n1; ++n) col_axis_to_ws(n, a, P, L, leaf, W, smax);
         const double wm = wave_max(smax);
         __syncthreads();
         double *red = P;

@@ -114,10 +114,31 @@ def test_plain_ppm_values_pass_the_check(oracle_mod):
     assert fails == 0
 
 
-def test_adversarial_bias_falls_back_everywhere_bitwise(oracle_mod):
+def test_limiter_makes_predictions_pass_and_keeps_valid_rows(oracle_mod):
+    w = blast_single_leaf()
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    P = o.padded(U)[0]
+    V = oracle_mod.reconstruct_values(P)
+    rng = np.random.default_rng(12)
+    for (i, j, k) in [(2, 3, 4), (3, 3, 3), (4, 5, 2), (7, 4, 4), (1, 6, 3)]:
+        c = (k + 1) * 100 + (j + 1) * 10 + (i + 1)
+        for f in range(7):
+            nb, s, x = oracle_mod.mlp_features(P, i, j, k, f)
+            if x is None:
+                continue
+            # valid values (plain PPM) pass through the limiter unchanged
+            assert np.array_equal(oracle_mod.mlp_limit(nb, V[c, :, f]), V[c, :, f])
+            # noisy predictions are limited into values that pass the check
+            noisy = V[c, :, f] + 0.3 * s * rng.normal(size=26)
+            lim = oracle_mod.mlp_limit(nb, noisy)
+            assert oracle_mod.mlp_row_ok(nb, lim, f)
+
+
+def test_nan_network_falls_back_everywhere_bitwise(oracle_mod):
     w = blast_single_leaf()
     p = _params(8)
-    p[8064:] = 10.0                   # every output ten sigmas out of bounds
+    p[8064:] = np.nan                 # every non-flat row fails the check
     o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
     dt = o.dt(w.U)
     Up, ap = o.step(dt, w.U)
