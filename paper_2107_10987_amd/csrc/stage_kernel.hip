@@ -42,11 +42,9 @@ __device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     const double dl = q0 - qm;
     const double dr = qp - q0;
     const double d = 0.5 * (qp - qm);
-    double m = fabs(d);
-    const double a = 2.0 * fabs(dl);
-    const double b = 2.0 * fabs(dr);
-    m = (a < m) ? a : m;
-    m = (b < m) ? b : m;
+    // all three operands are finite and non-negative, so fmin (one FP64
+    // instruction) selects exactly what the comparisons would
+    const double m = fmin(fmin(fabs(d), 2.0 * fabs(dl)), 2.0 * fabs(dr));
     return (dl * dr > 0.0) ? copysign(m, d) : 0.0;
 }
 
@@ -104,30 +102,34 @@ __device__ __forceinline__ void point_state(const double *P, int c, int dx, int 
 }
 
 // Euler flux along axis n (run-time) of one reconstructed state; returns |u_n| + c.
+// The dual-energy switch is evaluated without contraction, exactly as
+// written; the flux arithmetic after it may fuse multiply-adds.
 __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double xq, double yq,
                                                const Phys &ph, double F[NF]) {
     const double rho = U[RHO], E = U[EGAS], tau = U[TAU];
     const double rinv = 1.0 / rho;
     const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
-    const double vn = (n == 0) ? v0 : ((n == 1) ? v1 : v2);
-    // velocity relative to the grid rotating about z: u = v - omega x r
-    const double ux = v0 + ph.omega * yq;
-    const double uy = v1 - ph.omega * xq;
-    const double un = (n == 0) ? ux : ((n == 1) ? uy : v2);
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
     if (eint < ph.eta1 * E) eint = pow(tau, ph.gamma);
-    const double p = (ph.gamma - 1.0) * eint;
-    const double cs = sqrt(ph.gamma * p * rinv);
-    F[RHO] = rho * un;
-    const double fx = U[SX] * un, fy = U[SY] * un, fz = U[SZ] * un;
-    F[SX] = (n == 0) ? fx + p : fx;
-    F[SY] = (n == 1) ? fy + p : fy;
-    F[SZ] = (n == 2) ? fz + p : fz;
-    F[EGAS] = E * un + p * vn;
-    F[TAU] = tau * un;
-    F[SPC] = U[SPC] * un;
-    return fabs(un) + cs;
+    {
+#pragma clang fp contract(fast)
+        const double vn = (n == 0) ? v0 : ((n == 1) ? v1 : v2);
+        // velocity relative to the grid rotating about z: u = v - omega x r
+        const double ux = v0 + ph.omega * yq;
+        const double uy = v1 - ph.omega * xq;
+        const double un = (n == 0) ? ux : ((n == 1) ? uy : v2);
+        const double p = (ph.gamma - 1.0) * eint;
+        const double cs = sqrt(ph.gamma * p * rinv);
+        F[RHO] = rho * un;
+        F[SX] = (n == 0) ? U[SX] * un + p : U[SX] * un;
+        F[SY] = (n == 1) ? U[SY] * un + p : U[SY] * un;
+        F[SZ] = (n == 2) ? U[SZ] * un + p : U[SZ] * un;
+        F[EGAS] = E * un + p * vn;
+        F[TAU] = tau * un;
+        F[SPC] = U[SPC] * un;
+        return fabs(un) + cs;
+    }
 }
 
 // Euler flux along axis N of one reconstructed state; returns |u_N| + c.
@@ -444,11 +446,14 @@ __device__ __forceinline__ double point_flux_acc(int n, const double UL[NF], con
     double FL[NF], FR[NF];
     const double sl = side_flux_rt(n, UL, xq, yq, ph, FL);
     const double sr = side_flux_rt(n, UR, xq, yq, ph, FR);
-    const double s = sl > sr ? sl : sr;
+    const double s = fmax(sl, sr);
+    {
+#pragma clang fp contract(fast)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const double Fq = 0.5 * (FL[f] + FR[f]) - 0.5 * s * (UR[f] - UL[f]);
-        acc[f] = acc[f] + w * Fq;
+        for (int f = 0; f < NF; ++f) {
+            const double Fq = 0.5 * (FL[f] + FR[f]) - 0.5 * s * (UR[f] - UL[f]);
+            acc[f] = acc[f] + w * Fq;
+        }
     }
     return s;
 }

@@ -50,7 +50,7 @@ def test_binary_32768_stage_sampled_parity(torch, binary, schedule):
     rng = np.random.default_rng(11)
     starts = np.sort(rng.choice(w.n - 8, 12, replace=False))
     for l0 in starts:
-        Uo, ao = o.stage(1, dt, w.U, int(l0), int(l0) + 8)
+        Uo, ao = o.stage(1, dt, w.U, l0=int(l0), l1=int(l0) + 8)
         got = U1[l0:l0 + 8].reshape(8, 7, -1)
         ref = Uo.reshape(8, 7, -1)
         for f in range(7):
