@@ -25,6 +25,14 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// LDS staging of a wave's 64 rows: bf16 rows of 64 padded to a 68-element
+// (136 B) stride, FP32 output rows of 32 padded to 34 (136 B).  Rows written
+// one per lane then fall in different banks, and the 8-byte MFMA operand
+// loads stay aligned.
+constexpr int LDA = 68;
+constexpr int LDY = 34;
+constexpr int STAGE_ELEMS = 64 * LDA;   // bf16 elements per wave
+
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -63,10 +71,10 @@ __device__ __forceinline__ void layer(const uint16_t *A, const uint16_t *W, int 
         v4s b[NTILE];
 #pragma unroll
         for (int nt = 0; nt < NTILE; ++nt)
-            b[nt] = *(const v4s *)(W + (16 * nt + r) * 64 + 16 * kb + 4 * q);
+            b[nt] = *(const v4s *)(W + (16 * nt + r) * 64 + 16 * kb + 4 * q);   // global, stride 64
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const v4s a = *(const v4s *)(A + (16 * mt + r) * 64 + 16 * kb + 4 * q);
+            const v4s a = *(const v4s *)(A + (16 * mt + r) * LDA + 16 * kb + 4 * q);
 #pragma unroll
             for (int nt = 0; nt < NTILE; ++nt) z[mt][nt] = mfma(a, b[nt], z[mt][nt]);
         }
@@ -88,7 +96,7 @@ __device__ __forceinline__ void hidden_out(v4f z[4][4], const float *bias, uint1
                 const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
                 const float zz = z[mt][nt][i] + bias[col];
                 const uint16_t a = bf16_bits(gelu(zz));
-                S[row * 64 + col] = a;
+                S[row * LDA + col] = a;
                 if (zsave && row < nrows) {
                     zsave[(size_t)(row0 + row) * 64 + col] = zz;
                     asave[(size_t)(row0 + row) * 64 + col] = a;
@@ -97,7 +105,7 @@ __device__ __forceinline__ void hidden_out(v4f z[4][4], const float *bias, uint1
 }
 
 // Forward pass of the 64 rows staged (as bf16 inputs) in S; the 26 outputs of
-// row r land in Y[r][0..25] (FP32, stride 32, aliasing S).
+// row r land in Y[r][0..25] (FP32, row stride LDY, aliasing S).
 __device__ __forceinline__ void forward64(uint16_t *S, const uint16_t *Wb, const float *par, int lane,
                                           float *z1s, uint16_t *a1s, float *z2s, uint16_t *a2s, int row0,
                                           int nrows) {
@@ -117,7 +125,7 @@ __device__ __forceinline__ void forward64(uint16_t *S, const uint16_t *Wb, const
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * mt + 4 * q + i, col = 16 * nt + c;
-                if (col < OUT) Y[row * 32 + col] = y[mt][nt][i] + par[P_B3 + col];
+                if (col < OUT) Y[row * LDY + col] = y[mt][nt][i] + par[P_B3 + col];
             }
 }
 
@@ -129,7 +137,7 @@ __device__ __forceinline__ void forward64(uint16_t *S, const uint16_t *Wb, const
 
 // Forward of B rows of X [B][34] (float32); keeps what the backward needs.
 __global__ void __launch_bounds__(256) mlp_train_forward(MlpTrain t, const float *X, int B) {
-    __shared__ uint16_t S[4][64 * 64];
+    __shared__ uint16_t S[4][STAGE_ELEMS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row0 = (blockIdx.x * 4 + w) * 64;
     if (row0 >= B) return;                        // wave-uniform
@@ -139,19 +147,19 @@ __global__ void __launch_bounds__(256) mlp_train_forward(MlpTrain t, const float
     for (int k = 0; k < 64; ++k) {
         const float v = (lane < nrows && k < IN) ? X[(size_t)(row0 + lane) * IN + k] : 0.f;
         const uint16_t b = bf16_bits(v);
-        s[lane * 64 + k] = b;
+        s[lane * LDA + k] = b;
         if (lane < nrows) t.xb[(size_t)(row0 + lane) * 64 + k] = b;
     }
     forward64(s, t.wb, t.par, lane, t.z1, t.a1, t.z2, t.a2, row0, nrows);
     const float *Y = (const float *)s;
     if (lane < nrows)
-        for (int o = 0; o < OUT; ++o) t.y[(size_t)(row0 + lane) * 32 + o] = Y[lane * 32 + o];
+        for (int o = 0; o < OUT; ++o) t.y[(size_t)(row0 + lane) * 32 + o] = Y[lane * LDY + o];
 }
 
 // dY = 2 (y - T) / (B * 26); dZ2 = (dY W3) * gelu'(z2); dZ1 = (dZ2 W2) * gelu'(z1).
 // One wave per 64 rows; per-row loss partials.
 __global__ void __launch_bounds__(256) mlp_train_backward_rows(MlpTrain t, const float *T, int B) {
-    __shared__ uint16_t S[4][64 * 64];
+    __shared__ uint16_t S[4][STAGE_ELEMS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row0 = (blockIdx.x * 4 + w) * 64;
     if (row0 >= B) return;
@@ -167,7 +175,7 @@ __global__ void __launch_bounds__(256) mlp_train_backward_rows(MlpTrain t, const
             d = scale * r;
             t.dy[(size_t)(row0 + lane) * 32 + o] = d;
         }
-        s[lane * 64 + o] = bf16_bits(d);   // dY as the A operand (k = output index)
+        s[lane * LDA + o] = bf16_bits(d);   // dY as the A operand (k = output index)
     }
     if (lane < nrows) t.loss_rows[row0 + lane] = loss;
     // dA2[r][h] = sum_o dY[r][o] W3[o][h]: B operand[k = o][n = h] = W3[o][h] -> W3T copy
@@ -183,7 +191,7 @@ __global__ void __launch_bounds__(256) mlp_train_backward_rows(MlpTrain t, const
                 if (row < nrows) d = z[mt][nt][i] * gelu_grad(t.z2[(size_t)(row0 + row) * 64 + col]);
                 if (row < nrows) t.dz2f[(size_t)(row0 + row) * 64 + col] = d;
                 const uint16_t b = bf16_bits(d);
-                s[row * 64 + col] = b;
+                s[row * LDA + col] = b;
                 if (row < nrows) t.dz2[(size_t)(row0 + row) * 64 + col] = b;
             }
     layer<4>(s, t.wbT + WB_W2T, lane, z);
@@ -377,7 +385,7 @@ __device__ __forceinline__ bool row_ok(const double nb[27], const double val[26]
 // the check.  Writes the FP64 point values and a per-cell pass flag.
 __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
     __shared__ double B12[NF * RB12 * RB12 * RB12];      // 96,768 B
-    __shared__ uint16_t S[4][64 * 64];                   // 32,768 B
+    __shared__ uint16_t S[4][STAGE_ELEMS];               // 34,816 B
     const int leaf = m.leaf0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // gather: interior from U, the rest through the ghost map (skipping the
@@ -443,12 +451,12 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
             float v = 0.f;
             if (k < 27) v = (float)((nb[k] - qc) * rs);
             else if (k < IN) v = (k - 27 == f) ? 1.f : 0.f;
-            s[lane * 64 + k] = (live && !flat) ? bf16_bits(v) : (uint16_t)0;
+            s[lane * LDA + k] = (live && !flat) ? bf16_bits(v) : (uint16_t)0;
         }
         forward64(s, m.wb, m.par, lane, nullptr, nullptr, nullptr, nullptr, 0, 0);
         double val[26];
 #pragma unroll
-        for (int d = 0; d < 26; ++d) val[d] = flat ? qc : qc + sigma * (double)ys[lane * 32 + d];
+        for (int d = 0; d < 26; ++d) val[d] = flat ? qc : qc + sigma * (double)ys[lane * LDY + d];
         if (!flat) limit_row(nb, val);
         const bool ok = !live || flat || row_ok(nb, val, f);
         const unsigned long long mask = __ballot(ok);
