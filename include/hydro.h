@@ -218,8 +218,9 @@ const double *hydro_amax_device(const hydro_t *h);
 int hydro_check(hydro_t *h, void *stream);
 
 /* Stage-kernel timing.  enable = 1 starts recording a HIP event pair around
- * every stage launch on its stream (up to 4096 launches, then recording
- * stops); enable = 0 stops.  If total_ms / launches are non-NULL the call
+ * every stage launch of a step on its stream (up to 4096 launches, then
+ * recording stops; the signal-speed pre-pass of hydro_signal_speed and
+ * hydro_dt is not recorded); enable = 0 stops.  If total_ms / launches are non-NULL the call
  * first waits for the recorded events and reports the summed kernel time (ms)
  * and the number of launches timed since the previous report, then clears
  * them.  Event objects are created on the first enable. */

@@ -483,7 +483,7 @@ int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax) {
     if (rc) return rc;
     if (!g->U || !amax) return fail(h, HYDRO_EINVAL, "null U or amax");
     if ((rc = set_device(h))) return rc;
-    return run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, amax, 0);
+    return run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, amax, 0, nullptr, false);
 }
 
 int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out) {
@@ -510,7 +510,7 @@ int hydro_dt(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev) {
     if (!g->U || !dt_dev) return fail(h, HYDRO_EINVAL, "null U or dt_dev");
     if (!(cfl > 0.0) || !isfinite(cfl)) return fail(h, HYDRO_EINVAL, "cfl must be > 0");
     if ((rc = set_device(h))) return rc;
-    if ((rc = run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, h->amax, 0))) return rc;
+    if ((rc = run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, h->amax, 0, nullptr, false))) return rc;
     hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
 }

@@ -51,6 +51,27 @@ def test_device_dt_step_matches_host_dt(torch):
         hy.close()
 
 
+def test_timing_counts_the_stage_launches_of_steps(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: stage timing, 3 device-dt steps of sedov-32^3 (RK2 and RK3)", flush=True)
+    w = sedov_uniform(4)
+    for rk in (2, 3):
+        hy = Hydro(max_leaves=w.n, rk_order=rk)
+        try:
+            g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+            dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+            hy.timing(True)
+            hy.dt(g, w.cfl, dt_dev)          # pre-pass: not recorded
+            hy.signal_speed(g)               # not recorded either
+            for _ in range(3):
+                hy.step_dev(g, w.cfl, dt_dev)
+            ms, n = hy.timing(False)
+            assert n == 3 * rk and ms > 0.0
+            assert hy.timing(False) == (0.0, 0)   # cleared by the report
+        finally:
+            hy.close()
+
+
 @pytest.mark.parametrize("schedule", ["column", "tiled", "auto"])
 def test_graph_replay_matches_eager(torch, schedule):
     from paper_2107_10987_amd.hydro import Hydro
