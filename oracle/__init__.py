@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 
 class Phys(C.Structure):
     _fields_ = [("gamma", C.c_double), ("omega", C.c_double),
-                ("eta1", C.c_double), ("eta2", C.c_double), ("centre_only", C.c_int)]
+                ("eta1", C.c_double), ("eta2", C.c_double), ("centre_only", C.c_int),
+                ("reflux", C.c_int)]
 
 
 _lib = None
@@ -105,7 +106,7 @@ def ppm(q) -> tuple[float, float]:
 def point_flux(n: int, UL, UR, xq, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
     UL, UR, xq = _f64(UL), _f64(UR), _f64(xq)
     F = np.zeros(7)
-    ph = Phys(gamma, omega, eta1, eta2, 0)
+    ph = Phys(gamma, omega, eta1, eta2, 0, 0)
     a = lib().oracle_point_flux(int(n), _p(UL), _p(UR), _p(xq), C.byref(ph), _p(F))
     return F, a
 
@@ -121,13 +122,13 @@ class Oracle:
     """
 
     def __init__(self, tree, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1, threads=None,
-                 centre_only=False):
+                 centre_only=False, reflux=False):
         a = tree.arrays()
         self._keep = a
         self.n = tree.n
         self.dx = a["dx"]
         self.origin = a["origin"]
-        self.phys = Phys(gamma, omega, eta1, eta2, int(centre_only))
+        self.phys = Phys(gamma, omega, eta1, eta2, int(centre_only), int(reflux))
         self.threads = threads or default_threads()
         ip = C.POINTER(C.c_int)
         self._t = lib().oracle_tree_create(_p(a["nb"], C.c_int), _p(a["bc"], C.c_int), self.n,
@@ -267,7 +268,7 @@ def leaf_rhs(P, dx, origin, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
     dU = np.zeros((NF, NC))
     amax = C.c_double()
     org = _f64(origin)
-    ph = Phys(gamma, omega, eta1, eta2, 0)
+    ph = Phys(gamma, omega, eta1, eta2, 0, 0)
     lib().oracle_leaf_rhs(_p(P), float(dx), _p(org), C.byref(ph), _p(dU), C.byref(amax))
     return dU, amax.value
 
@@ -286,7 +287,7 @@ def leaf_fluxes(P, dx, origin, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1):
     P = _f64(P)
     Fn = np.zeros((3, 9, 8, 8, NF))
     org = _f64(origin)
-    ph = Phys(gamma, omega, eta1, eta2, 0)
+    ph = Phys(gamma, omega, eta1, eta2, 0, 0)
     a = lib().oracle_leaf_fluxes(_p(P), float(dx), _p(org), C.byref(ph), _p(Fn))
     return Fn, a
 

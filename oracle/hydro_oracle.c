@@ -385,12 +385,10 @@ void oracle_leaf_rhs(const double *P, double dx, const double origin[3], const o
     free(V);
 }
 
-void oracle_leaf_rhs_from_values(const double *V, const double *P, double dx, const double origin[3],
-                                 const oracle_phys *ph, double *dU, double *amax)
+/* L(U) from the face fluxes Fn: flux divergence plus the rotating-frame
+ * source (Omega sy, -Omega sx) of the cell values in P. */
+static void rhs_from_fluxes(const double *Fn, const double *P, double dx, const oracle_phys *ph, double *dU)
 {
-    double *Fn = (double *)malloc(sizeof(double) * 3 * 9 * NX * NX * NFLD);
-    double smax = oracle_leaf_fluxes_from_values(V, dx, origin, ph, Fn);
-    /* flux divergence plus the rotating-frame source (Omega sy, -Omega sx) */
     double idx = 1.0 / dx;
 #define FX(i, j, k, f) Fn[((((long)0 * 9 + (i)) * NX + (j)) * NX + (k)) * NFLD + (f)]
 #define FY(i, j, k, f) Fn[((((long)1 * 9 + (j)) * NX + (i)) * NX + (k)) * NFLD + (f)]
@@ -412,7 +410,14 @@ void oracle_leaf_rhs_from_values(const double *V, const double *P, double dx, co
 #undef FX
 #undef FY
 #undef FZ
-    *amax = smax;
+}
+
+void oracle_leaf_rhs_from_values(const double *V, const double *P, double dx, const double origin[3],
+                                 const oracle_phys *ph, double *dU, double *amax)
+{
+    double *Fn = (double *)malloc(sizeof(double) * 3 * 9 * NX * NX * NFLD);
+    *amax = oracle_leaf_fluxes_from_values(V, dx, origin, ph, Fn);
+    rhs_from_fluxes(Fn, P, dx, ph, dU);
     free(Fn);
 }
 
@@ -441,6 +446,100 @@ static int ssp_coeffs(int order, int stage, double *a, double *b)
     return -2;
 }
 
+/* The leaves one level finer across face (n, s) of `leaf`, s = -1 or +1.
+ * Returns 1 with ch[o1 + 2 o2] = the child whose offsets along the two other
+ * axes (in increasing axis order) are o1, o2, when the region next to the
+ * face, at the leaf's level, is split into leaves of the next level; 0 when
+ * a leaf of the same or a coarser level covers it, or beyond an outflow
+ * boundary; -1 when those children are not leaves (tree not 2:1 balanced). */
+static int finer_across(const tree_t *t, int leaf, int n, int s, int ch[4])
+{
+    const int l = t->level[leaf];
+    long q[3];
+    for (int a = 0; a < 3; ++a) q[a] = t->coord[3 * leaf + a];
+    q[n] += s;
+    if (q[n] < 0 || q[n] >= t->dim[l][n]) {
+        if (t->bc[n] != 0) return 0;
+        q[n] = (q[n] + t->dim[l][n]) % t->dim[l][n];
+    }
+    for (int lc = l; lc >= 0; --lc) {
+        long r[3];
+        for (int a = 0; a < 3; ++a) r[a] = q[a] >> (l - lc);
+        if (t->slot[lc][(r[2] * t->dim[lc][1] + r[1]) * t->dim[lc][0] + r[0]] >= 0) return 0;
+    }
+    if (l + 1 > t->lmax) return -1;
+    const int t1 = (n == 0) ? 1 : 0, t2 = (n == 2) ? 1 : 2;
+    for (int o2 = 0; o2 < 2; ++o2)
+        for (int o1 = 0; o1 < 2; ++o1) {
+            long r[3];
+            r[n] = 2 * q[n] + (s > 0 ? 0 : 1);
+            r[t1] = 2 * q[t1] + o1;
+            r[t2] = 2 * q[t2] + o2;
+            const int c = t->slot[l + 1][(r[2] * t->dim[l + 1][1] + r[1]) * t->dim[l + 1][0] + r[0]];
+            if (c < 0) return -1;
+            ch[o1 + 2 * o2] = c;
+        }
+    return 1;
+}
+
+static int plain_values(const double *P, void *ctx, double *V)
+{
+    (void)ctx;
+    reconstruct_block(P, V);
+    return 0;
+}
+
+/* Face fluxes Fn of one leaf for the state U: ghost fill, point values from
+ * `values` (which returns its count of fallback cells), fluxes. */
+static int fluxes_of_leaf(const tree_t *t, const double *U, int leaf, const double *dx,
+                          const double *origin, const oracle_phys *ph, oracle_values_fn values,
+                          void *ctx, double *P, double *V, double *Fn, double *smax, int *nfb)
+{
+    if (oracle_fill_padded(t, U, leaf, leaf + 1, P)) return -1;
+    const int nf = values(P, ctx, V);
+    if (nfb) *nfb = nf;
+    *smax = oracle_leaf_fluxes_from_values(V, dx[leaf], origin + 3L * leaf, ph, Fn);
+    return 0;
+}
+
+/* Flux correction at coarse/fine faces.  The paper runs the scheme on an
+ * AMR octree (section IV-B) without saying how fluxes are matched where a
+ * leaf meets finer ones; the reading here is the usual conservative one: the
+ * coarse face flux through a face shared with four finer cells is the mean
+ * of those cells' own face fluxes (each a flux density over a quarter of the
+ * coarse face), so what leaves the fine cells enters the coarse cell. */
+static int reflux_fluxes(const tree_t *t, const double *U, int leaf, const double *dx,
+                         const double *origin, const oracle_phys *ph, oracle_values_fn values, void *ctx,
+                         double *P, double *V, double *Fc, double *Fn)
+{
+    for (int n = 0; n < 3; ++n)
+        for (int side = 0; side < 2; ++side) {
+            int ch[4];
+            const int r = finer_across(t, leaf, n, side ? 1 : -1, ch);
+            if (r < 0) return -1;
+            if (r == 0) continue;
+            const int fi = side ? NX : 0;   /* this leaf's face on the shared plane */
+            const int fc = side ? 0 : NX;   /* the children's face on it */
+            for (int o2 = 0; o2 < 2; ++o2)
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    double sm;
+                    if (fluxes_of_leaf(t, U, ch[o1 + 2 * o2], dx, origin, ph, values, ctx, P, V, Fc, &sm, NULL))
+                        return -1;
+                    for (int c1 = 4 * o1; c1 < 4 * o1 + 4; ++c1)
+                        for (int c2 = 4 * o2; c2 < 4 * o2 + 4; ++c2) {
+                            const int a = 2 * (c1 - 4 * o1), b = 2 * (c2 - 4 * o2);
+                            for (int f = 0; f < NFLD; ++f) {
+#define FC(u, v) Fc[((((long)n * 9 + fc) * NX + (a + (u))) * NX + (b + (v))) * NFLD + f]
+                                const double m = ((FC(0, 0) + FC(1, 0)) + (FC(0, 1) + FC(1, 1))) * 0.25;
+#undef FC
+                                Fn[((((long)n * 9 + fi) * NX + c1) * NX + c2) * NFLD + f] = m;
+                            }
+                        }
+                }
+        }
+    return 0;
+}
+
 int oracle_stage(const void *t, int stage, double dt, const double *Uin, const double *Un,
                  const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
                  double *Uout, double *amax)
@@ -452,15 +551,33 @@ int oracle_stage_rk(const void *t, int order, int stage, double dt, const double
                     const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
                     double *Uout, double *amax)
 {
+    return oracle_stage_with(t, order, stage, dt, Uin, Un, dx, origin, ph, l0, l1, Uout, amax,
+                             plain_values, NULL, NULL);
+}
+
+int oracle_stage_with(const void *tp, int order, int stage, double dt, const double *Uin,
+                      const double *Un, const double *dx, const double *origin, const oracle_phys *ph,
+                      int l0, int l1, double *Uout, double *amax, oracle_values_fn values, void *ctx,
+                      int *fallback)
+{
+    const tree_t *t = (const tree_t *)tp;
     double ca, cb;
     if (ssp_coeffs(order, stage, &ca, &cb)) return -2;
+    const long nfx = 3L * 9 * NX * NX * NFLD;
     double *P = (double *)malloc(sizeof(double) * NFLD * NPAD);
+    double *P2 = (double *)malloc(sizeof(double) * NFLD * NPAD);
+    double *V = (double *)malloc(sizeof(double) * RB * RB * RB * 26 * NFLD);
+    double *Fn = (double *)malloc(sizeof(double) * nfx);
+    double *Fc = (double *)malloc(sizeof(double) * nfx);
     double *dU = (double *)malloc(sizeof(double) * NFLD * NCELL);
     int rc = 0;
     for (int leaf = l0; leaf < l1 && rc == 0; ++leaf) {
-        rc = oracle_fill_padded(t, Uin, leaf, leaf + 1, P);
+        rc = fluxes_of_leaf(t, Uin, leaf, dx, origin, ph, values, ctx, P, V, Fn, &amax[leaf],
+                            fallback ? &fallback[leaf] : NULL);
         if (rc) break;
-        oracle_leaf_rhs(P, dx[leaf], origin + 3L * leaf, ph, dU, &amax[leaf]);
+        if (ph->reflux && (rc = reflux_fluxes(t, Uin, leaf, dx, origin, ph, values, ctx, P2, V, Fc, Fn)))
+            break;
+        rhs_from_fluxes(Fn, P, dx[leaf], ph, dU);
         const long base = (long)leaf * NFLD * NCELL;
         for (long e = 0; e < NFLD * NCELL; ++e) {
             double u = Uin[base + e];
@@ -477,6 +594,10 @@ int oracle_stage_rk(const void *t, int order, int stage, double dt, const double
             }
     }
     free(dU);
+    free(Fc);
+    free(Fn);
+    free(V);
+    free(P2);
     free(P);
     return rc;
 }

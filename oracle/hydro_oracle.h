@@ -26,7 +26,14 @@ typedef struct {
     double eta1;    /* dual-energy pressure switch at face points */
     double eta2;    /* dual-energy tracer resync threshold after a step */
     int centre_only; /* 1: the old scheme, one flux point at each face centre */
+    int reflux;      /* 1: coarse faces shared with finer leaves take the mean of
+                        the finer faces' fluxes */
 } oracle_phys;
+
+/* Point values of one padded block into V (layout of
+ * oracle_reconstruct_values); returns the number of cells that fell back to
+ * plain PPM (0 for plain PPM itself). */
+typedef int (*oracle_values_fn)(const double *P, void *ctx, double *V);
 
 /* One-dimensional PPM on five equally spaced values q[0..4] = q_{-2..2}:
  * left and right interface values of the middle cell. */
@@ -74,7 +81,9 @@ void oracle_leaf_rhs(const double *P, double dx, const double origin[3], const o
 
 /* One SSP-RK2 stage for leaves [l0, l1): stage 1: Uout = Uin + dt L(Uin);
  * stage 2: Uout = (Un + (Uin + dt L(Uin)))/2 followed by the tracer resync.
- * Ghosts come from Uin over the whole tree. amax[l] for l in [l0, l1). */
+ * Ghosts come from Uin over the whole tree. amax[l] for l in [l0, l1).
+ * Returns 0, -1 if a ghost cell or (with reflux) a finer neighbour is not
+ * covered by leaves, -2 for an unknown stage. */
 int oracle_stage(const void *t, int stage, double dt, const double *Uin, const double *Un,
                  const double *dx, const double *origin, const oracle_phys *ph,
                  int l0, int l1, double *Uout, double *amax);
@@ -86,6 +95,14 @@ int oracle_stage(const void *t, int stage, double dt, const double *Uin, const d
 int oracle_stage_rk(const void *t, int order, int stage, double dt, const double *Uin, const double *Un,
                     const double *dx, const double *origin, const oracle_phys *ph, int l0, int l1,
                     double *Uout, double *amax);
+
+/* oracle_stage_rk with the point values of every leaf (and, with reflux, of
+ * the finer leaves next to it) from `values`; fallback[l] (if non-NULL)
+ * receives the leaf's own fallback count. */
+int oracle_stage_with(const void *t, int order, int stage, double dt, const double *Uin,
+                      const double *Un, const double *dx, const double *origin, const oracle_phys *ph,
+                      int l0, int l1, double *Uout, double *amax, oracle_values_fn values, void *ctx,
+                      int *fallback);
 
 /* Maximum signal speed of every leaf in [l0, l1) for the state U. */
 int oracle_signal_speed(const void *t, const double *U, const double *dx, const double *origin,

@@ -310,39 +310,17 @@ void oracle_learned_values(const double *P, const float *par, double *V, int *ne
 
 /* One SSP-RK2 stage of leaves [l0, l1) with the learned reconstruction;
  * otherwise as oracle_stage.  fallback[l] counts leaf l's fallback cells. */
+static int learned_values(const double *P, void *ctx, double *V)
+{
+    int nn, nf;
+    oracle_learned_values(P, (const float *)ctx, V, &nn, &nf);
+    return nf;
+}
+
 int oracle_stage_learned(const void *t, const float *par, int stage, double dt, const double *Uin,
                          const double *Un, const double *dx, const double *origin, const oracle_phys *ph,
                          int l0, int l1, double *Uout, double *amax, int *fallback)
 {
-    if (stage != 1 && stage != 2) return -2;
-    double *P = (double *)malloc(sizeof(double) * NFC * NPADC);
-    double *V = (double *)malloc(sizeof(double) * RBC * RBC * RBC * 26 * NFC);
-    double *dU = (double *)malloc(sizeof(double) * NFC * 512);
-    int rc = 0;
-    for (int leaf = l0; leaf < l1; ++leaf) {
-        rc = oracle_fill_padded(t, Uin, leaf, leaf + 1, P);
-        if (rc) break;
-        int nn, nf;
-        oracle_learned_values(P, par, V, &nn, &nf);
-        if (fallback) fallback[leaf] = nf;
-        oracle_leaf_rhs_from_values(V, P, dx[leaf], origin + 3L * leaf, ph, dU, &amax[leaf]);
-        const long base = (long)leaf * NFC * 512;
-        for (long e = 0; e < NFC * 512; ++e) {
-            double u = Uin[base + e];
-            Uout[base + e] = stage == 1 ? u + dt * dU[e] : 0.5 * (Un[base + e] + (u + dt * dU[e]));
-        }
-        if (stage == 2)
-            for (long c = 0; c < 512; ++c) {
-                double rho = Uout[base + c], E = Uout[base + 4 * 512 + c];
-                double sx = Uout[base + 512 + c], sy = Uout[base + 1024 + c], sz = Uout[base + 1536 + c];
-                double rinv = 1.0 / rho;
-                double ek = 0.5 * (sx * sx + sy * sy + sz * sz) * rinv;
-                double eint = E - ek;
-                if (eint > ph->eta2 * E) Uout[base + 5 * 512 + c] = pow(eint, 1.0 / ph->gamma);
-            }
-    }
-    free(dU);
-    free(V);
-    free(P);
-    return rc;
+    return oracle_stage_with(t, 2, stage, dt, Uin, Un, dx, origin, ph, l0, l1, Uout, amax,
+                             learned_values, (void *)par, fallback);
 }

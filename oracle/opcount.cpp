@@ -72,6 +72,7 @@ double opcount_point_flux(int n, const double *ul, const double *ur, const doubl
     ph.eta1 = cd(eta1);
     ph.eta2 = cd(0.1);
     ph.centre_only = 0;
+    ph.reflux = 0;
     cd a = oracle_point_flux(n, UL, UR, xq, &ph, Fc);
     for (int f = 0; f < 7; ++f) F[f] = Fc[f].v;
     return a.v;
@@ -92,6 +93,7 @@ void opcount_leaf_rhs(const double *P, double dx, const double *origin, double g
     ph.eta1 = cd(eta1);
     ph.eta2 = cd(0.1);
     ph.centre_only = 0;
+    ph.reflux = 0;
     cd am;
     oracle_leaf_rhs(Pc, cd(dx), org, &ph, dUc, &am);
     for (int i = 0; i < 7 * 512; ++i) dU[i] = dUc[i].v;
