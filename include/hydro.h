@@ -72,7 +72,9 @@ typedef struct hydro_params {
     int32_t scheme;     /* 0: fluxes at the 9 points of every face (new scheme);
                            1: at face centres only, weight 1 (the paper's old scheme,
                            section IV-B); same reconstruction                      */
-    int32_t reserved;
+    int32_t reflux;     /* 1: flux correction at coarse/fine faces (every grid then
+                           carries face_flags and the reflux list from
+                           hydro_reflux_map); 0: none                              */
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */
@@ -87,6 +89,9 @@ typedef struct hydro_grid {
     double omega;              /* frame rotation rate about z                        */
     double gamma;              /* ratio of specific heats, > 1                       */
     void *stream;              /* hipStream_t; NULL = the null stream                */
+    const int32_t *face_flags; /* device [n] from hydro_reflux_map, or NULL without  */
+    const int32_t *reflux;     /*   reflux; device [n_reflux][26] correction list    */
+    int32_t n_reflux;          /*   entries in the list (may be 0)                   */
 } hydro_grid;
 
 /* Octree description used to build the ghost map (host memory). */
@@ -114,6 +119,24 @@ int hydro_destroy(hydro_t *h);
  * Returns HYDRO_EINVAL if the tree is not 2:1 balanced or a leaf is outside
  * the box.  Synchronous; needs no handle and no GPU. */
 int hydro_ghost_map(const hydro_tree *t, int32_t *map);
+
+/* Coarse/fine face lists of a tree for the flux correction (host memory,
+ * caller-owned).  The paper runs the scheme on an AMR octree (section IV-B)
+ * and does not say how fluxes are matched where a leaf meets finer ones; the
+ * library uses the conservative correction: each stage, the flux through a
+ * coarse face shared with four finer cells is replaced by the mean of those
+ * cells' own Simpson face fluxes.
+ *   face_flags[t->n]: bit f (f = 2 axis + side, side 1 = the +axis face) set
+ *     when face f of the leaf borders leaves one level finer (the leaf is
+ *     corrected), bit 8+f when it borders a coarser leaf (the leaf's flux
+ *     through face f is kept for its coarse neighbour).
+ *   entries[t->n][26] (capacity): one entry per corrected leaf, *n_entries of
+ *     them: {leaf, mask of bits 0-5, child[6][4]}; child[f][o1 + 2 o2] is the
+ *     finer leaf across face f whose offsets along the two other axes (in
+ *     increasing axis order) are o1, o2; -1 for faces without finer leaves.
+ * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face or a
+ * leaf is outside the box.  Synchronous; needs no handle and no GPU. */
+int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries);
 
 /* One full SSP Runge-Kutta step of all leaves, in place on g->U (Shu-Osher
  * form, ghosts refreshed from the stage input before each stage, tracer

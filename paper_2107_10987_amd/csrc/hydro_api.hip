@@ -28,6 +28,7 @@ struct hydro_t {
     int *queue = nullptr;      // persistent launches: [2]
     int *leaf_done = nullptr;  // [max_leaves]
     double *tile_amax = nullptr;  // [max_leaves][3]
+    double *bflux = nullptr;   // flux correction: [max_leaves][6][7][64]
     int num_cu = 0;
     int32_t table[HYDRO_NBUCKET];  // schedule per launch-size bucket (HYDRO_SCHED_AUTO)
     bool table_loaded = false;
@@ -123,6 +124,13 @@ int check_grid(hydro_t *h, const hydro_grid *g) {
     if (!g->dx || !g->origin || !g->ghost_map) return fail(h, HYDRO_EINVAL, "null dx/origin/ghost_map");
     if (!(g->gamma > 1.0) || !isfinite(g->gamma)) return fail(h, HYDRO_EINVAL, "gamma must be > 1");
     if (!isfinite(g->omega)) return fail(h, HYDRO_EINVAL, "omega must be finite");
+    if (h->p.reflux) {
+        if (!g->face_flags) return fail(h, HYDRO_EINVAL, "reflux needs g->face_flags (hydro_reflux_map)");
+        if (g->n_reflux < 0 || g->n_reflux > g->n) return fail(h, HYDRO_EINVAL, "n_reflux out of range");
+        if (g->n_reflux > 0 && !g->reflux) return fail(h, HYDRO_EINVAL, "reflux list is NULL");
+    } else if (g->face_flags || g->n_reflux) {
+        return fail(h, HYDRO_EINVAL, "grid carries reflux lists but the handle was created without reflux");
+    }
     if (g->n_launch < 0) return fail(h, HYDRO_EINVAL, "n_launch < 0");
     if (g->n_launch > 0) {
         if (!g->launch_off) return fail(h, HYDRO_EINVAL, "launch_off is NULL");
@@ -136,6 +144,44 @@ int check_grid(hydro_t *h, const hydro_grid *g) {
 }
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+// Leaf lookup by (level, leaf coordinates) of a validated tree.
+struct TreeIndex {
+    const hydro_tree *t = nullptr;
+    int lmax = 0;
+    std::unordered_map<uint64_t, int32_t> owner;
+    static uint64_t key(int l, int64_t x, int64_t y, int64_t z) {
+        return ((uint64_t)l << 60) | ((uint64_t)z << 40) | ((uint64_t)y << 20) | (uint64_t)x;
+    }
+    int build(const hydro_tree *tree) {
+        t = tree;
+        if (!t || !t->level || !t->coord || t->n <= 0) return fail(nullptr, HYDRO_EINVAL, "null or empty tree");
+        if ((int64_t)t->n * NC > INT32_MAX) return fail(nullptr, HYDRO_EINVAL, "too many leaves for int32 cell ids");
+        for (int a = 0; a < 3; ++a)
+            if (t->nb[a] <= 0 || (t->bc[a] != 0 && t->bc[a] != 1))
+                return fail(nullptr, HYDRO_EINVAL, "bad nb/bc");
+        for (int i = 0; i < t->n; ++i) {
+            if (t->level[i] < 0 || t->level[i] > 20) return fail(nullptr, HYDRO_EINVAL, "level out of range");
+            lmax = t->level[i] > lmax ? t->level[i] : lmax;
+        }
+        owner.reserve((size_t)t->n * 2);
+        for (int i = 0; i < t->n; ++i) {
+            const int32_t *c = t->coord + 3 * (size_t)i;
+            const int l = t->level[i];
+            for (int a = 0; a < 3; ++a)
+                if (c[a] < 0 || (int64_t)c[a] >= ((int64_t)t->nb[a] << l))
+                    return fail(nullptr, HYDRO_EINVAL, "leaf outside the box");
+            if (!owner.emplace(key(l, c[0], c[1], c[2]), i).second)
+                return fail(nullptr, HYDRO_EINVAL, "duplicate leaf");
+        }
+        return HYDRO_OK;
+    }
+    // the leaf at level l with leaf coordinates (x, y, z), or -1
+    int32_t leaf(int l, int64_t x, int64_t y, int64_t z) const {
+        auto it = owner.find(key(l, x, y, z));
+        return it == owner.end() ? -1 : it->second;
+    }
+};
 
 int set_device(hydro_t *h) {
     hipError_t e = hipSetDevice(h->device);
@@ -201,6 +247,9 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.mlp_val = nullptr;
     a.mlp_ok = nullptr;
     a.centre_only = h->p.scheme == 1;
+    const bool reflux = h->p.reflux && stage != 0;
+    a.face_flags = reflux ? g->face_flags : nullptr;
+    a.bflux = reflux ? h->bflux : nullptr;
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
@@ -233,6 +282,22 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         hipError_t e = hydro_launch_stage(a, s);
         if (e != hipSuccess) return hip_fail(h, e, "stage launch");
         if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used++ + 1], s);
+    }
+    if (reflux && g->n_reflux > 0) {
+        // after every launch of the stage: the finer leaves' fluxes are all kept
+        RefluxArgs r;
+        r.U = Uout;
+        r.bflux = h->bflux;
+        r.entries = g->reflux;
+        r.dx = g->dx;
+        r.dt = dt;
+        r.dt_dev = dt_dev;
+        r.cb = a.cb;
+        r.last = a.last;
+        r.ph = a.ph;
+        r.status = h->status;
+        hipError_t e = hydro_launch_reflux(r, g->n_reflux, s);
+        if (e != hipSuccess) return hip_fail(h, e, "reflux launch");
     }
     return HYDRO_OK;
 }
@@ -379,6 +444,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (p->rk_order != 0 && p->rk_order != 2 && p->rk_order != 3)
         return fail(nullptr, HYDRO_EINVAL, "rk_order must be 2 or 3");
     if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, HYDRO_EINVAL, "scheme must be 0 or 1");
+    if (p->reflux != 0 && p->reflux != 1) return fail(nullptr, HYDRO_EINVAL, "reflux must be 0 or 1");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
         return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
@@ -411,6 +477,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->leaf_done, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->tile_amax, n * 3 * sizeof(double));
+    if (e == hipSuccess && p->reflux) e = hipMalloc((void **)&h->bflux, n * BFLUX_STRIDE * sizeof(double));
     if (e == hipSuccess) e = alloc_mlp(h, n);
     if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMemset(h->leaf_done, 0, n * sizeof(int));
@@ -440,6 +507,7 @@ int hydro_destroy(hydro_t *h) {
     if (h->queue) (void)hipFree(h->queue);
     if (h->leaf_done) (void)hipFree(h->leaf_done);
     if (h->tile_amax) (void)hipFree(h->tile_amax);
+    if (h->bflux) (void)hipFree(h->bflux);
     for (void *b : h->mlp_bufs) (void)hipFree(b);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
@@ -751,35 +819,12 @@ const char *hydro_last_error(const hydro_t *h) { return h ? h->err.c_str() : g_c
 // ---------------------------------------------------------------------------
 
 int hydro_ghost_map(const hydro_tree *t, int32_t *map) {
-    if (!t || !map || !t->level || !t->coord || t->n <= 0)
-        return fail(nullptr, HYDRO_EINVAL, "null or empty tree");
-    if ((int64_t)t->n * NC > INT32_MAX) return fail(nullptr, HYDRO_EINVAL, "too many leaves for int32 cell ids");
-    for (int a = 0; a < 3; ++a)
-        if (t->nb[a] <= 0 || (t->bc[a] != 0 && t->bc[a] != 1))
-            return fail(nullptr, HYDRO_EINVAL, "bad nb/bc");
-    int lmax = 0;
-    for (int i = 0; i < t->n; ++i) {
-        if (t->level[i] < 0 || t->level[i] > 20) return fail(nullptr, HYDRO_EINVAL, "level out of range");
-        lmax = t->level[i] > lmax ? t->level[i] : lmax;
-    }
-    auto key = [](int l, int64_t x, int64_t y, int64_t z) -> uint64_t {
-        return ((uint64_t)l << 60) | ((uint64_t)z << 40) | ((uint64_t)y << 20) | (uint64_t)x;
-    };
-    std::unordered_map<uint64_t, int32_t> owner;
-    owner.reserve((size_t)t->n * 2);
-    for (int i = 0; i < t->n; ++i) {
-        const int32_t *c = t->coord + 3 * (size_t)i;
-        const int l = t->level[i];
-        for (int a = 0; a < 3; ++a)
-            if (c[a] < 0 || (int64_t)c[a] >= ((int64_t)t->nb[a] << l))
-                return fail(nullptr, HYDRO_EINVAL, "leaf outside the box");
-        if (!owner.emplace(key(l, c[0], c[1], c[2]), i).second)
-            return fail(nullptr, HYDRO_EINVAL, "duplicate leaf");
-    }
-    auto find = [&](int l, const int64_t g[3]) -> int32_t {
-        auto it = owner.find(key(l, g[0] >> 3, g[1] >> 3, g[2] >> 3));
-        return it == owner.end() ? -1 : it->second;
-    };
+    if (!map) return fail(nullptr, HYDRO_EINVAL, "null map");
+    TreeIndex ti;
+    int rc = ti.build(t);
+    if (rc) return rc;
+    const int lmax = ti.lmax;
+    auto find = [&](int l, const int64_t g[3]) -> int32_t { return ti.leaf(l, g[0] >> 3, g[1] >> 3, g[2] >> 3); };
     auto local = [](const int64_t g[3]) -> int32_t {
         return (int32_t)(((g[2] & 7) * NX + (g[1] & 7)) * NX + (g[0] & 7));
     };
@@ -827,6 +872,60 @@ int hydro_ghost_map(const hydro_tree *t, int32_t *map) {
                     m[s++] = src;
                 }
     }
+    return HYDRO_OK;
+}
+
+int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries) {
+    if (!face_flags || !entries || !n_entries) return fail(nullptr, HYDRO_EINVAL, "null output");
+    TreeIndex ti;
+    int rc = ti.build(t);
+    if (rc) return rc;
+    for (int i = 0; i < t->n; ++i) face_flags[i] = 0;
+    int32_t m = 0;
+    for (int i = 0; i < t->n; ++i) {
+        const int l = t->level[i];
+        const int32_t *c = t->coord + 3 * (size_t)i;
+        int32_t *e = entries + (size_t)m * REFLUX_ENTRY;
+        int mask = 0;
+        for (int k = 0; k < 4 * NBFACE; ++k) e[2 + k] = -1;
+        for (int phi = 0; phi < NBFACE; ++phi) {
+            const int n = phi >> 1, side = phi & 1;
+            int64_t q[3] = {c[0], c[1], c[2]};
+            q[n] += side ? 1 : -1;
+            const int64_t dim = (int64_t)t->nb[n] << l;
+            if (q[n] < 0 || q[n] >= dim) {
+                if (t->bc[n] != 0) continue;   // outflow boundary: no neighbour
+                q[n] = (q[n] + dim) % dim;
+            }
+            bool covered = false;   // a leaf of this level or coarser
+            for (int lc = l; lc >= 0 && !covered; --lc)
+                covered = ti.leaf(lc, q[0] >> (l - lc), q[1] >> (l - lc), q[2] >> (l - lc)) >= 0;
+            if (covered) continue;
+            const int t1 = (n == 0) ? 1 : 0, t2 = (n == 2) ? 1 : 2;
+            for (int o2 = 0; o2 < 2; ++o2)
+                for (int o1 = 0; o1 < 2; ++o1) {
+                    int64_t r[3];
+                    r[n] = 2 * q[n] + (side ? 0 : 1);
+                    r[t1] = 2 * q[t1] + o1;
+                    r[t2] = 2 * q[t2] + o2;
+                    const int32_t ch = ti.leaf(l + 1, r[0], r[1], r[2]);
+                    if (ch < 0)
+                        return fail(nullptr, HYDRO_EINVAL,
+                                    "face " + std::to_string(phi) + " of leaf " + std::to_string(i) +
+                                        " is neither covered nor refined once (tree not 2:1 balanced)");
+                    e[2 + 4 * phi + o1 + 2 * o2] = ch;
+                    face_flags[ch] |= 1 << (8 + 2 * n + (1 - side));
+                }
+            mask |= 1 << phi;
+        }
+        if (mask) {
+            face_flags[i] |= mask;
+            e[0] = i;
+            e[1] = mask;
+            ++m;
+        }
+    }
+    *n_entries = m;
     return HYDRO_OK;
 }
 

@@ -64,6 +64,29 @@ struct StageArgs {
     // learned reconstruction (null: plain PPM)
     const double *mlp_val;    // [n][896][7][26] learned point values
     const uint8_t *mlp_ok;    // [n][896]
+    // flux correction at coarse/fine faces (null: none)
+    const int32_t *face_flags;  // [n]: bits 0-5 corrected faces, 8-13 faces kept for a coarser leaf
+    double *bflux;              // [n][6][7][64] Simpson flux of flagged boundary faces
+};
+
+// Boundary faces of a leaf: f = 2 axis + side (side 1 = +axis); the 64 face
+// cells of a face by (t1, t2) = the two other axes in increasing order,
+// index t1 + 8 t2.
+constexpr int NBFACE = 6;
+constexpr int BFLUX_STRIDE = NBFACE * NF * NX * NX;   // doubles per leaf
+constexpr int REFLUX_ENTRY = 26;                      // {leaf, mask, child[6][4]}
+
+struct RefluxArgs {
+    double *U;                // [n][7][512] stage output, corrected in place
+    const double *bflux;      // [n][6][7][64]
+    const int32_t *entries;   // [m][26]
+    const double *dx;         // [n]
+    double dt;
+    const double *dt_dev;     // if set, dt is read from device memory
+    double cb;                // weight of dt L in the stage combine
+    int last;                 // last stage: tracer resync of the corrected cells
+    Phys ph;
+    Status *status;
 };
 
 enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
@@ -73,6 +96,7 @@ enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
 // Launchers implemented in the kernel translation unit.
 hipError_t hydro_upload_ghost_table(const uint16_t *table);
 hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
+hipError_t hydro_launch_reflux(const hydro::RefluxArgs &r, int n_entries, hipStream_t s);
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
                            hipStream_t s);
 hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,

@@ -256,6 +256,26 @@ __device__ __forceinline__ void gather_block(double *P, const double *U, const i
     }
 }
 
+// Whether interior cell c lies on one of the faces set in mask (bit
+// 2 axis + side, side 1 = the +axis face).
+__device__ __forceinline__ bool corrected_cell(int mask, int c) {
+    const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+    return ((mask & 1) && i == 0) || ((mask & 2) && i == NX - 1) || ((mask & 4) && j == 0) ||
+           ((mask & 8) && j == NX - 1) || ((mask & 16) && k == 0) || ((mask & 32) && k == NX - 1);
+}
+
+// Keep the Simpson flux F of boundary face (axis n, index fn in 0..8 along
+// n, face cell t1 + 8 t2) when the leaf's flags ask for it.
+__device__ __forceinline__ void store_bflux(const StageArgs &a, int leaf, int n, int fn, int t12,
+                                            const double F[NF]) {
+    if (fn != 0 && fn != NX) return;
+    const int phi = 2 * n + (fn == NX ? 1 : 0);
+    if (!(a.face_flags[leaf] & (0x101 << phi))) return;
+    double *o = a.bflux + (size_t)leaf * BFLUX_STRIDE + phi * NF * NX * NX + t12;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) o[f * NX * NX] = F[f];
+}
+
 // Flux divergence sum dsum (per field, over the three axes) -> L(U), the
 // rotating-frame source, the stage combine, the tracer resync and the store
 // of one interior cell; non-physical results are reported in a.status.
@@ -280,7 +300,10 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
 #pragma unroll
         for (int f = 0; f < NF; ++f) o[f] = a.ca * a.Un[base + (size_t)f * NC] + a.cb * (u[f] + dt * L[f]);
     }
-    if (a.last) {
+    // cells on a face the coarse/fine correction changes get their resync
+    // after the correction, in the reflux pass
+    const int cmask = a.face_flags ? (a.face_flags[leaf] & 63) : 0;
+    if (a.last && !(cmask && corrected_cell(cmask, c))) {
         // dual-energy resync of the tracer after the full step
         const double rinv = 1.0 / o[RHO];
         const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
@@ -336,6 +359,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     face_flux<0>(P, tid, dx, org, a.ph, a.centre_only, F0, smax);
     face_flux<1>(P, tid, dx, org, a.ph, a.centre_only, F1, smax);
     face_flux<2>(P, tid, dx, org, a.ph, a.centre_only, F2, smax);
+    if (a.bflux) {
+        // face r of axis 0: (i, j, k) = (r % 9, r / 9 % 8, r / 72); axis 1:
+        // (r % 8, r / 8 % 9, r / 72); axis 2: (r % 8, r / 8 % 8, r / 64)
+        store_bflux(a, leaf, 0, tid % 9, (tid / 9) % 8 + 8 * (tid / 72), F0);
+        store_bflux(a, leaf, 1, (tid / 8) % 9, tid % 8 + 8 * (tid / 72), F1);
+        store_bflux(a, leaf, 2, tid / 64, tid % 64, F2);
+    }
     __syncthreads();  // the input block is dead from here on
 
     double *Fl = P;                      // [f][axis][576]
@@ -463,7 +493,7 @@ __device__ __forceinline__ double point_flux_acc(int n, const double UL[NF], con
 // column `col` and cell index `cell` in -1..8.
 __device__ __forceinline__ void column_axis(int N, const double *P, int col, int cell, double dx,
                                             double ox, double oy, double oz, const Phys &ph,
-                                            const StageArgs &a, int leaf, double dsum[NF],
+                                            const StageArgs &a, int leaf, bool live, double dsum[NF],
                                             double &smax) {
     const int c1 = col & 7, c2 = col >> 3;
     // cell B on the walk, in (x, y, z): axis N takes `cell`, t1 < t2 take c1, c2
@@ -525,6 +555,7 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
             smax = s > smax ? s : smax;
         }
     }
+    if (a.bflux && live) store_bflux(a, leaf, N, cell, col, acc);
 #pragma unroll
     for (int f = 0; f < NF; ++f) dsum[f] = shfl_down1(acc[f]) - acc[f];
 }
@@ -555,7 +586,7 @@ __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const 
     const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
     double d[NF];
     double sm = 0.0;
-    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, d, sm);
+    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
     smax = L.live && sm > smax ? sm : smax;
     if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
         const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
@@ -670,6 +701,75 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
             a.queue[0] = 0;
             a.queue[1] = 0;
             __threadfence();
+        }
+    }
+}
+
+// Flux correction of one coarse leaf after a stage: for each face shared
+// with four finer leaves, the stage used the leaf's own flux Fc through the
+// face; the conservative flux is the mean Ff of the finer faces' fluxes, so
+// the face cell's L(U) changes by -(Ff - Fc)/dx on a +axis face and by
+// +(Ff - Fc)/dx on a -axis face, and the stage output by cb dt times that.
+// Faces are taken one after another (a cell on an edge or corner can sit on
+// two or three of them); then the corrected cells get the tracer resync the
+// stage kernel left out, and the non-physical check.
+constexpr int NTR = NF * NX * NX;   // 448 threads: (field, face cell)
+
+__global__ void __launch_bounds__(NTR) reflux_kernel(RefluxArgs r) {
+    const int32_t *e = r.entries + (size_t)blockIdx.x * REFLUX_ENTRY;
+    const int leaf = e[0], mask = e[1];
+    const int tid = threadIdx.x;
+    const int f = tid >> 6, t12 = tid & 63;
+    const int t1 = t12 & 7, t2 = t12 >> 3;
+    const double dt = r.dt_dev ? *r.dt_dev : r.dt;
+    const double idx = 1.0 / r.dx[leaf];
+    double *Ul = r.U + (size_t)leaf * LEAF_STRIDE;
+    for (int phi = 0; phi < NBFACE; ++phi) {
+        if (!((mask >> phi) & 1)) continue;   // uniform over the workgroup
+        const int n = phi >> 1, side = phi & 1;
+        const int child = e[2 + 4 * phi + (t1 >> 2) + 2 * (t2 >> 2)];
+        const int cphi = 2 * n + (1 - side);   // the finer leaves' face on the shared plane
+        const double *Fch = r.bflux + (size_t)child * BFLUX_STRIDE + (cphi * NF + f) * NX * NX;
+        const int a0 = 2 * (t1 & 3), b0 = 2 * (t2 & 3);
+        const double Ff = ((Fch[a0 + NX * b0] + Fch[a0 + 1 + NX * b0]) +
+                           (Fch[a0 + NX * (b0 + 1)] + Fch[a0 + 1 + NX * (b0 + 1)])) * 0.25;
+        const double Fc = r.bflux[(size_t)leaf * BFLUX_STRIDE + (phi * NF + f) * NX * NX + t12];
+        const double dF = Ff - Fc;
+        const double dL = (side ? -dF : dF) * idx;
+        const int cn = side ? NX - 1 : 0;
+        const int i = (n == 0) ? cn : t1;
+        const int j = (n == 1) ? cn : ((n == 0) ? t1 : t2);
+        const int k = (n == 2) ? cn : t2;
+        double *u = Ul + (size_t)f * NC + (k * NX + j) * NX + i;
+        *u = *u + r.cb * (dt * dL);
+        __syncthreads();
+    }
+    for (int c = tid; c < NC; c += NTR) {
+        if (!corrected_cell(mask, c)) continue;
+        double o[NF];
+#pragma unroll
+        for (int g = 0; g < NF; ++g) o[g] = Ul[(size_t)g * NC + c];
+        if (r.last) {
+            const double rinv = 1.0 / o[RHO];
+            const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
+            const double eint = o[EGAS] - ek;
+            if (eint > r.ph.eta2 * o[EGAS]) {
+                o[TAU] = pow(eint, 1.0 / r.ph.gamma);
+                Ul[(size_t)TAU * NC + c] = o[TAU];
+            }
+        }
+        bool bad = !(o[RHO] > 0.0);
+        int badf = bad ? RHO : -1;
+#pragma unroll
+        for (int g = 0; g < NF; ++g)
+            if (!isfinite(o[g]) && !bad) {
+                bad = true;
+                badf = g;
+            }
+        if (bad && atomicCAS(&r.status->flag, 0, 1) == 0) {
+            r.status->leaf = leaf;
+            r.status->cell = c;
+            r.status->field = badf;
         }
     }
 }
@@ -789,6 +889,12 @@ __global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double 
         for (int w = 1; w < 4; ++w) r = red[w] < r ? red[w] : r;
         *dt_out = cfl * r;
     }
+}
+
+hipError_t hydro_launch_reflux(const RefluxArgs &r, int n_entries, hipStream_t s) {
+    if (n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reflux_kernel, dim3(n_entries), dim3(NTR), 0, s, r);
+    return hipGetLastError();
 }
 
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,

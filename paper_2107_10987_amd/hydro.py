@@ -16,8 +16,10 @@ LIB_PATH = os.path.join(HERE, "_build", "libhydro.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS = 0, -1, -2, -3, -4
 NX, NF, NC, NGHOST = 8, 7, 512, 2232
+REFLUX_ENTRY = 26
 
-EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_step", "hydro_stage",
+EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_reflux_map", "hydro_step",
+           "hydro_stage",
            "hydro_signal_speed", "hydro_reconstruct", "hydro_step_dev", "hydro_dt",
            "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_mlp_load",
            "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
@@ -37,14 +39,15 @@ class Params(C.Structure):
     _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
                 ("schedule", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
                 ("tune_cache", C.c_char_p), ("mlp_batch", C.c_int32), ("rk_order", C.c_int32),
-                ("scheme", C.c_int32), ("reserved", C.c_int32)]
+                ("scheme", C.c_int32), ("reflux", C.c_int32)]
 
 
 class Grid(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_launch", C.c_int32), ("launch_off", C.POINTER(C.c_int32)),
                 ("U", C.c_void_p), ("dx", C.c_void_p), ("origin", C.c_void_p),
                 ("ghost_map", C.c_void_p), ("omega", C.c_double), ("gamma", C.c_double),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("face_flags", C.c_void_p), ("reflux", C.c_void_p),
+                ("n_reflux", C.c_int32)]
 
 
 class Tree(C.Structure):
@@ -68,6 +71,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
     L.hydro_destroy.argtypes = [vp]
     L.hydro_ghost_map.argtypes = [C.POINTER(Tree), C.POINTER(C.c_int32)]
+    ip = C.POINTER(C.c_int32)
+    L.hydro_reflux_map.argtypes = [C.POINTER(Tree), ip, ip, ip]
     L.hydro_step.argtypes = [vp, C.POINTER(Grid), C.c_double, dp]
     L.hydro_stage.argtypes = [vp, C.POINTER(Grid), C.c_int, C.c_double, vp, vp, vp, vp]
     L.hydro_signal_speed.argtypes = [vp, C.POINTER(Grid), vp]
@@ -102,18 +107,38 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     return L
 
 
-def ghost_map(tree) -> np.ndarray:
-    """Ghost map int32 [n][2232] of a workloads.Tree, built by the library."""
-    L = load()
+def _tree_struct(tree):
     a = tree.arrays()
     t = Tree(tree.n, (C.c_int32 * 3)(*a["nb"]), (C.c_int32 * 3)(*a["bc"]),
              a["level"].ctypes.data_as(C.POINTER(C.c_int32)),
              a["coord"].ctypes.data_as(C.POINTER(C.c_int32)))
+    return t, a
+
+
+def ghost_map(tree) -> np.ndarray:
+    """Ghost map int32 [n][2232] of a workloads.Tree, built by the library."""
+    L = load()
+    t, _keep = _tree_struct(tree)
     out = np.empty((tree.n, NGHOST), dtype=np.int32)
     rc = L.hydro_ghost_map(C.byref(t), out.ctypes.data_as(C.POINTER(C.c_int32)))
     if rc:
         raise HydroError(rc, L.hydro_last_error(None).decode())
     return out
+
+
+def reflux_map(tree):
+    """Coarse/fine face lists of a workloads.Tree, built by the library:
+    (face_flags int32 [n], entries int32 [m][26])."""
+    L = load()
+    t, _keep = _tree_struct(tree)
+    flags = np.empty(tree.n, dtype=np.int32)
+    ent = np.empty((tree.n, REFLUX_ENTRY), dtype=np.int32)
+    m = C.c_int32()
+    ip = C.POINTER(C.c_int32)
+    rc = L.hydro_reflux_map(C.byref(t), flags.ctypes.data_as(ip), ent.ctypes.data_as(ip), C.byref(m))
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
+    return flags, ent[:m.value].copy()
 
 
 def _ptr(t) -> int:
@@ -129,16 +154,18 @@ class Hydro:
 
     def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
                  schedule: str = "auto", tune_cache: str | None = None, learned: bool = False,
-                 mlp_batch: int = 4096, rk_order: int = 2, centre_only: bool = False):
+                 mlp_batch: int = 4096, rk_order: int = 2, centre_only: bool = False,
+                 reflux: bool = False):
         import torch
         self.torch = torch
         self.L = load()
         self.device = device
         self.schedule = schedule
         self.learned = learned
+        self.reflux = reflux
         self.p = Params(int(max_leaves), int(device), int(bool(learned)), SCHEDULES[schedule],
                         float(eta1), float(eta2), tune_cache.encode() if tune_cache else None,
-                        int(mlp_batch), int(rk_order), int(bool(centre_only)), 0)
+                        int(mlp_batch), int(rk_order), int(bool(centre_only)), int(bool(reflux)))
         h = C.c_void_p()
         rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
         if rc:
@@ -283,5 +310,14 @@ class DeviceGrid:
         else:
             self._off, nl, offp = None, 0, None
         s = 0 if stream is None else int(stream.cuda_stream)
+        self.flags = self.reflux = None
+        nr = 0
+        if hy.reflux:
+            fl, ent = reflux_map(tree)
+            self.flags = torch.as_tensor(fl, device=dev)
+            self.reflux = torch.as_tensor(ent, device=dev)
+            nr = ent.shape[0]
+        self.n_reflux = nr
         self.c = Grid(tree.n, nl, offp, _ptr(self.U), _ptr(self.dx), _ptr(self.origin),
-                      _ptr(self.gmap), float(omega), float(gamma), s or None)
+                      _ptr(self.gmap), float(omega), float(gamma), s or None,
+                      _ptr(self.flags) or None, (_ptr(self.reflux) if nr else 0) or None, nr)

@@ -1,0 +1,237 @@
+"""GPU parity of the flux correction at coarse/fine faces against the CPU
+oracle with the same correction, for every schedule; conservation of the
+totals on a periodic AMR mesh; the 4096-leaf polytrope in uneven launches;
+RK3; graph replay; and the learned path's fallback reproducing the plain
+corrected step.
+
+Tolerance (FP64): per field, max |gpu - oracle| / max |oracle_f| <= 1e-12.
+The library adds cb dt (L_corrected - L) to the stage output while the
+oracle forms the stage from the corrected L directly, so the two round
+differently in the corrected cells (a few ulp of the cell value)."""
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd.workloads import (PERIODIC, LeafSet, conserved_from_primitive,
+                                            rotating_polytrope, uneven_batches)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+G = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _amr_tree():
+    ls = LeafSet((2, 2, 2), (PERIODIC,) * 3, (0.0, 0.0, 0.0), 1.0 / 16,
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+    ls.refine(0, (0, 0, 0))
+    ls.refine(0, (1, 1, 1))
+    return ls.tree()
+
+
+def _state(tree, seed=5):
+    rng = np.random.default_rng(seed)
+    x = tree.cell_centres()
+    ph = rng.uniform(0, 2 * np.pi, size=6)
+    r2 = ((x[:, 0] - 0.45) ** 2 + (x[:, 1] - 0.5) ** 2 + (x[:, 2] - 0.55) ** 2)
+    rho = 1.0 + 2.0 * np.exp(-r2 / 0.02) + 0.2 * np.sin(2 * np.pi * x[:, 1] + ph[0])
+    vx = 0.5 + 0.3 * np.sin(2 * np.pi * (x[:, 1] + x[:, 2]) + ph[1])
+    vy = -0.4 + 0.2 * np.sin(2 * np.pi * (x[:, 0] + x[:, 2]) + ph[2])
+    vz = 0.3 * np.sin(2 * np.pi * (x[:, 0] + x[:, 1]) + ph[3])
+    p = 1.0 + 0.5 * np.exp(-r2 / 0.03) + 0.1 * np.sin(2 * np.pi * x[:, 0] + ph[4])
+    spc = rho * (0.5 + 0.4 * np.sin(2 * np.pi * x[:, 2] + ph[5]))
+    return np.ascontiguousarray(conserved_from_primitive(rho, vx, vy, vz, p, spc, G))
+
+
+def field_err(g, o):
+    g = np.asarray(g).reshape(g.shape[0], 7, -1)
+    o = np.asarray(o).reshape(o.shape[0], 7, -1)
+    return np.array([np.abs(g[:, f] - o[:, f]).max() / max(np.abs(o[:, f]).max(), 1e-300)
+                     for f in range(7)])
+
+
+@pytest.mark.parametrize("schedule", ["column", "face", "persistent", "tiled"])
+def test_reflux_stages_and_steps_match_oracle(torch, schedule):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: reflux, periodic AMR 22 leaves, schedule {schedule}", flush=True)
+    t = _amr_tree()
+    U = _state(t)
+    o = oracle.Oracle(t, G, 0.0, reflux=True)
+    hy = Hydro(max_leaves=t.n, schedule=schedule, reflux=True)
+    try:
+        g = hy.grid(t, torch.tensor(U, device="cuda"), 0.0, G)
+        assert g.n_reflux > 0
+        dt = o.dt(U)
+        # stage 1 alone
+        U1o, a1o = o.stage(1, dt, U)
+        U1 = torch.empty_like(g.U)
+        am = torch.zeros(t.n, dtype=torch.float64, device="cuda")
+        hy.stage(g, 1, dt, g.U, None, U1, am)
+        err = field_err(U1.cpu().numpy(), U1o)
+        print("stage 1 err", err, flush=True)
+        assert np.all(err <= TOL), err
+        assert np.abs(am.cpu().numpy() - a1o).max() <= TOL * a1o.max()
+        # three whole steps
+        Uo = U
+        for s in range(3):
+            amax = hy.step(g, dt)
+            Uo, amo = o.step(dt, Uo)
+            err = field_err(g.U.cpu().numpy(), Uo)
+            print(f"step {s} err", err, flush=True)
+            assert np.all(err <= TOL), err
+            dt = float(0.4 * np.min(t.dx / amo))
+    finally:
+        hy.close()
+
+
+def test_reflux_conserves_totals_on_gpu(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: reflux conservation, periodic AMR, 5 steps", flush=True)
+    t = _amr_tree()
+    U = _state(t, seed=9)
+    vol = t.dx ** 3
+    tot0 = np.einsum("n,nfc->f", vol, U.reshape(t.n, 7, -1))
+    scale = np.einsum("n,nfc->f", vol, np.abs(U).reshape(t.n, 7, -1))
+    res = {}
+    for on in (True, False):
+        hy = Hydro(max_leaves=t.n, reflux=on)
+        try:
+            g = hy.grid(t, torch.tensor(U, device="cuda"), 0.0, G)
+            dt = float(0.4 * np.min(t.dx / hy.signal_speed(g).cpu().numpy()))
+            for _ in range(5):
+                am = hy.step(g, dt)
+                dt = float(0.4 * np.min(t.dx / am))
+            res[on] = g.U.cpu().numpy()
+        finally:
+            hy.close()
+    for on, Ue in res.items():
+        err = np.abs(np.einsum("n,nfc->f", vol, Ue.reshape(t.n, 7, -1)) - tot0) / scale
+        print("reflux", on, "relative total change", err, flush=True)
+        if on:
+            assert np.all(err[[0, 1, 2, 3, 4, 6]] <= 1e-14), err
+        else:
+            assert err[0] > 1e-9
+
+
+def test_reflux_polytrope_uneven_launches(torch):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: reflux, rotating polytrope 4096 leaves, uneven launches, tiled+column auto", flush=True)
+    w = rotating_polytrope()
+    off = uneven_batches(w.n)
+    o = oracle.Oracle(w.tree, w.gamma, w.omega, reflux=True)
+    hy = Hydro(max_leaves=w.n, schedule="auto", reflux=True)
+    try:
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        print("coarse leaves corrected:", g.n_reflux, flush=True)
+        assert g.n_reflux > 0
+        dt = float(w.cfl * np.min(w.tree.dx / o.signal_speed(w.U)))
+        hy.step(g, dt)
+        Uo, _ = o.step(dt, w.U)
+        err = field_err(g.U.cpu().numpy(), Uo)
+        print("polytrope reflux err", err, flush=True)
+        assert np.all(err <= TOL), err
+    finally:
+        hy.close()
+
+
+@pytest.mark.parametrize("schedule", ["column", "tiled"])
+def test_reflux_rk3_matches_oracle(torch, schedule):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: reflux RK3, periodic AMR, schedule {schedule}", flush=True)
+    t = _amr_tree()
+    U = _state(t, seed=11)
+    o = oracle.Oracle(t, G, 0.2, reflux=True)
+    hy = Hydro(max_leaves=t.n, schedule=schedule, reflux=True, rk_order=3)
+    try:
+        g = hy.grid(t, torch.tensor(U, device="cuda"), 0.2, G)
+        dt = o.dt(U)
+        hy.step(g, dt)
+        Uo, _ = o.step(dt, U, order=3)
+        err = field_err(g.U.cpu().numpy(), Uo)
+        assert np.all(err <= TOL), err
+    finally:
+        hy.close()
+
+
+def test_reflux_graph_replay_matches_eager(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: reflux, graph of 2 device-dt steps vs eager, 3 replays", flush=True)
+    t = _amr_tree()
+    U = _state(t, seed=12)
+    ref = Hydro(max_leaves=t.n, reflux=True)
+    gra = Hydro(max_leaves=t.n, reflux=True)
+    try:
+        s = torch.cuda.Stream()
+        ge = ref.grid(t, torch.tensor(U, device="cuda"), 0.0, G)
+        gg = gra.grid(t, torch.tensor(U, device="cuda"), 0.0, G, stream=s)
+        dte = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ref.dt(ge, 0.4, dte)
+        gra.dt(gg, 0.4, dtg)
+        torch.cuda.synchronize()
+        gra.graph_capture(gg, 0.4, dtg, 2)
+        torch.cuda.synchronize()
+        for r in range(3):
+            for _ in range(2):
+                ref.step_dev(ge, 0.4, dte)
+            gra.graph_launch(s)
+            torch.cuda.synchronize()
+            _ = (ge.U.sum() + 1.0).item()        # unrelated eager work between replays
+            assert torch.equal(ge.U, gg.U), r
+            assert dte.item() == dtg.item(), r
+    finally:
+        ref.close()
+        gra.close()
+
+
+def test_reflux_learned_nan_network_is_the_plain_corrected_step(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: reflux + learned with a NaN network == plain reflux step", flush=True)
+    t = _amr_tree()
+    U = _state(t, seed=13)
+    p = (np.random.default_rng(7).normal(size=8090) * 0.3).astype(np.float32)
+    p[8064:] = np.nan
+    plain = Hydro(max_leaves=t.n, schedule="column", reflux=True)
+    lrn = Hydro(max_leaves=t.n, schedule="column", reflux=True, learned=True)
+    try:
+        lrn.mlp_load(p)
+        ga = plain.grid(t, torch.tensor(U, device="cuda"), 0.0, G)
+        gb = lrn.grid(t, torch.tensor(U, device="cuda"), 0.0, G)
+        dt = float(0.4 * np.min(t.dx / plain.signal_speed(ga).cpu().numpy()))
+        plain.step(ga, dt)
+        lrn.step(gb, dt)
+        assert torch.equal(ga.U, gb.U)
+    finally:
+        plain.close()
+        lrn.close()
+
+
+def test_reflux_grid_checks(torch):
+    from paper_2107_10987_amd.hydro import EINVAL, Grid, Hydro, HydroError
+    t = _amr_tree()
+    U = torch.tensor(_state(t), device="cuda")
+    on = Hydro(max_leaves=t.n, reflux=True)
+    off = Hydro(max_leaves=t.n, reflux=False)
+    try:
+        g_on = on.grid(t, U.clone(), 0.0, G)
+        # a grid with reflux lists on a handle without reflux, and the reverse
+        with pytest.raises(HydroError) as e:
+            off.step(g_on, 1e-4)
+        assert e.value.code == EINVAL
+        g_off = off.grid(t, U.clone(), 0.0, G)
+        with pytest.raises(HydroError) as e:
+            on.step(g_off, 1e-4)
+        assert e.value.code == EINVAL
+    finally:
+        on.close()
+        off.close()

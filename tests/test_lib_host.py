@@ -110,3 +110,80 @@ def test_ghost_map_rejects_bad_tree():
     t.coord[1, 0] = 5               # outside the box
     with pytest.raises(hydro.HydroError):
         hydro.ghost_map(t)
+
+
+def _geometric_reflux(tree):
+    """Brute force: for each leaf face, the leaves one level finer that touch
+    it, found by locating points just across the face on a 2x2 grid of the
+    face's quarters."""
+    size = 8 * tree.dx
+    lo = tree.x0[None, :] + tree.coord * size[:, None]
+    box = tree.nb * 8 * tree.dx0
+    flags = np.zeros(tree.n, dtype=np.int64)
+    entries = {}
+    for leaf in range(tree.n):
+        for phi in range(6):
+            n, side = phi >> 1, phi & 1
+            t1, t2 = [a for a in range(3) if a != n]
+            kids = []
+            for o2 in range(2):
+                for o1 in range(2):
+                    x = lo[leaf] + 0.5 * size[leaf]
+                    x[n] = lo[leaf][n] + (size[leaf] + 0.25 * tree.dx[leaf] if side else -0.25 * tree.dx[leaf])
+                    x[t1] = lo[leaf][t1] + (0.25 + 0.5 * o1) * size[leaf]
+                    x[t2] = lo[leaf][t2] + (0.25 + 0.5 * o2) * size[leaf]
+                    r = x - tree.x0
+                    r = np.where(tree.bc == PERIODIC, np.mod(r, box), r)
+                    if np.any(r < 0) or np.any(r >= box):
+                        kids.append(None)
+                        continue
+                    x = tree.x0 + r
+                    inside = np.all((x[None, :] >= lo) & (x[None, :] < lo + size[:, None]), axis=1)
+                    kids.append(int(np.nonzero(inside)[0][0]))
+            if kids[0] is None or tree.level[kids[0]] <= tree.level[leaf]:
+                continue
+            assert all(tree.level[k] == tree.level[leaf] + 1 for k in kids)
+            flags[leaf] |= 1 << phi
+            entries.setdefault(leaf, {})[phi] = kids
+            for k in kids:
+                flags[k] |= 1 << (8 + 2 * n + (1 - side))
+    return flags, entries
+
+
+@needs_lib
+@pytest.mark.parametrize("make", ["uniform", "amr_per", "amr_mixed", "polytrope"])
+def test_reflux_map_matches_geometry(make):
+    if make == "uniform":
+        tree = uniform_tree((2, 2, 2), (PERIODIC,) * 3)
+    elif make == "polytrope":
+        tree = rotating_polytrope().tree
+    else:
+        bc = (PERIODIC,) * 3 if make == "amr_per" else (OUTFLOW, PERIODIC, OUTFLOW)
+        ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / 16,
+                     [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+        ls.refine(0, (0, 0, 0))
+        ls.refine(0, (1, 1, 1))
+        tree = ls.tree()
+    flags, ent = hydro.reflux_map(tree)
+    want_flags, want = _geometric_reflux(tree)
+    assert np.array_equal(flags, want_flags)
+    assert sorted(int(e[0]) for e in ent) == sorted(want)
+    for e in ent:
+        leaf, mask = int(e[0]), int(e[1])
+        assert mask == int(want_flags[leaf]) & 63
+        for phi in range(6):
+            got = [int(c) for c in e[2 + 4 * phi: 6 + 4 * phi]]
+            assert got == (want[leaf][phi] if phi in want[leaf] else [-1] * 4), (leaf, phi)
+    if make == "uniform":
+        assert len(ent) == 0 and not flags.any()
+
+
+@needs_lib
+def test_reflux_map_rejects_unbalanced_tree():
+    ls = LeafSet((2, 2, 2), (OUTFLOW,) * 3, (0, 0, 0), 1 / 16,
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+    ls.refine(0, (0, 0, 0))
+    ls.refine(1, (1, 1, 1))
+    with pytest.raises(hydro.HydroError) as e:
+        hydro.reflux_map(ls.tree())
+    assert e.value.code == hydro.EINVAL
