@@ -40,7 +40,7 @@ struct hydro_t {
     int mlp_batch = 0;
     int adam_t = 0;
     bool mlp_loaded = false;
-    double *mlp_val = nullptr;     // [max_leaves][896][7][26]
+    double *mlp_val = nullptr;     // [max_leaves][7][26][896]
     uint8_t *mlp_ok = nullptr;     // [max_leaves][896]
     uint16_t *ghost_pad = nullptr; // [2232]
     unsigned long long *fb_count = nullptr;

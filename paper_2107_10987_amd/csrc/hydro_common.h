@@ -62,7 +62,7 @@ struct StageArgs {
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
     // learned reconstruction (null: plain PPM)
-    const double *mlp_val;    // [n][896][7][26] learned point values
+    const double *mlp_val;    // [n][7][26][896] learned point values (field, dir, slot)
     const uint8_t *mlp_ok;    // [n][896]
     // flux correction at coarse/fine faces (null: none)
     const int32_t *face_flags;  // [n]: bits 0-5 corrected faces, 8-13 faces kept for a coarser leaf

@@ -43,7 +43,7 @@ struct MlpInfer {
     const uint16_t *ghost_pad;  // [2232] padded index of each ghost slot
     const uint16_t *wb;         // bf16 weights
     const float *par;           // float32 parameters (biases)
-    double *val;                // [n][896][7][26] limited point values
+    double *val;                // [n][7][26][896] limited point values (field, dir, slot)
     uint8_t *cell_ok;           // [n][896]
     unsigned long long *fb_count;  // cells that fell back to plain PPM
     int leaf0;

@@ -129,6 +129,66 @@ __device__ __forceinline__ void forward64(uint16_t *S, const uint16_t *Wb, const
             }
 }
 
+// GELU for inference: 0.5 z (1 + tanh u) = z / (1 + exp(-2u)),
+// u = C (z + A z^3), with the hardware exp2 and reciprocal (relative error
+// ~1e-7, far below the bfloat16 rounding that follows).
+__device__ __forceinline__ float gelu_fast(float z) {
+    const float u = GELU_C * (z + GELU_A * z * z * z);
+    const float e = __builtin_amdgcn_exp2f(-2.0f * 1.4426950408889634f * u);
+    return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// Inference forward pass of rows 16 mt .. 16 mt + 15 of the wave's staging
+// buffer S: each layer reads only those rows and writes its output over them
+// (the FP32 outputs Y use the same 136-byte row stride as the bf16 inputs), so
+// the four row tiles can run one after another with 16 accumulators.
+__device__ __forceinline__ void infer_tile(uint16_t *S, const uint16_t *Wb, const float *par, int lane,
+                                           int mt) {
+    // an opaque copy of the weight pointer: the 48 per-lane weight addresses
+    // are then formed here rather than hoisted out of the caller's loop,
+    // where they would hold 96 registers for the whole chunk
+    asm volatile("" : "+s"(Wb));
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int L = 0; L < 2; ++L) {
+        const uint16_t *W = Wb + (L == 0 ? WB_W1 : WB_W2);
+        const float *bias = par + (L == 0 ? P_B1 : P_B2);
+        v4f z[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) z[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const v4s a = *(const v4s *)(S + (16 * mt + r) * LDA + 16 * kb + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                z[nt] = mfma(a, *(const v4s *)(W + (16 * nt + r) * 64 + 16 * kb + 4 * q), z[nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * mt + 4 * q + i, col = 16 * nt + r;
+                S[row * LDA + col] = bf16_bits(gelu_fast(z[nt][i] + bias[col]));
+            }
+    }
+    v4f y[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const v4s a = *(const v4s *)(S + (16 * mt + r) * LDA + 16 * kb + 4 * q);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            y[nt] = mfma(a, *(const v4s *)(Wb + WB_W3 + (16 * nt + r) * 64 + 16 * kb + 4 * q), y[nt]);
+    }
+    float *Y = (float *)S;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * mt + 4 * q + i, col = 16 * nt + r;
+            if (col < OUT) Y[row * LDY + col] = y[nt][i] + par[P_B3 + col];
+        }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -377,38 +437,88 @@ __device__ __forceinline__ bool row_ok(const double nb[27], const double val[26]
     return ok;
 }
 
+// Limiter and check of one line of a row, on its two predicted values R (at
+// +d, dir27 index op) and L (at -d): the same expressions as limit_row and
+// row_ok, which only ever couple the two ends of one line.  nbR / nbL are the
+// neighbours in those directions.  Returns whether the line passes.
+__device__ __forceinline__ bool limit_check_line(double qc, double nbR, double nbL, int f, double &R,
+                                                 double &L) {
+    {
+        const double lo = qc < nbR ? qc : nbR, hi = qc < nbR ? nbR : qc;
+        R = (R < lo) ? lo : R;
+        R = (R > hi) ? hi : R;
+    }
+    {
+        const double lo = qc < nbL ? qc : nbL, hi = qc < nbL ? nbL : qc;
+        L = (L < lo) ? lo : L;
+        L = (L > hi) ? hi : L;
+    }
+    if ((R - qc) * (qc - L) <= 0.0) {
+        L = qc;
+        R = qc;
+    } else {
+        const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
+        if (D * M6 > D * D)
+            L = 3.0 * qc - 2.0 * R;
+        else if (D * M6 < -(D * D))
+            R = 3.0 * qc - 2.0 * L;
+    }
+    bool ok = true;
+    {
+        const double lo = qc < nbR ? qc : nbR, hi = qc < nbR ? nbR : qc;
+        ok = ok && (R >= lo && R <= hi);
+    }
+    {
+        const double lo = qc < nbL ? qc : nbL, hi = qc < nbL ? nbL : qc;
+        ok = ok && (L >= lo && L <= hi);
+    }
+    if (f == RHO || f == EGAS || f == TAU) ok = ok && (R > 0.0) && (L > 0.0);
+    if (f == SPC) ok = ok && (R >= 0.0) && (L >= 0.0);
+    if (!(L == qc && R == qc)) {
+        const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
+        const double lim = D * D + 1e-13 * fabs(D) * (fabs(L) + fabs(qc) + fabs(R));
+        ok = ok && ((R - qc) * (qc - L) > 0.0) && !(D * M6 > lim) && !(D * M6 < -lim);
+    }
+    return ok;
+}
+
 }  // namespace
 
-// One workgroup per leaf: stage cells -2..9 of every field in LDS, then each
-// wave takes chunks of 9 cells x 7 fields = 63 rows (lane = row): FP64
+// One workgroup per leaf, one field at a time: stage cells -2..9 of the field
+// in LDS (13.8 KB, so three workgroups share a compute unit), then each wave
+// takes chunks of 64 needed cells (lane = cell; 896 = 14 chunks): FP64
 // features, the network on MFMA, FP64 denormalisation, the plain limiter and
-// the check.  Writes the FP64 point values and a per-cell pass flag.
-__global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
-    __shared__ double B12[NF * RB12 * RB12 * RB12];      // 96,768 B
+// the check.  The FP64 point values go out as val[leaf][field][dir][slot]
+// (consecutive lanes, consecutive addresses); a cell passes when all seven of
+// its rows pass.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) mlp_infer_kernel(MlpInfer m) {
+    __shared__ double B12[RB12 * RB12 * RB12];           // 13,824 B
     __shared__ uint16_t S[4][STAGE_ELEMS];               // 34,816 B
+    __shared__ uint8_t okc[NSLOT];
     const int leaf = m.leaf0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // gather: interior from U, the rest through the ghost map (skipping the
-    // outermost ghost layer, which no 3x3x3 neighbourhood of a needed cell reads)
+    for (int c = tid; c < NSLOT; c += 256) okc[c] = 1;
     const double *Ul = m.U + (size_t)leaf * LEAF_STRIDE;
-    for (int e = tid; e < LEAF_STRIDE; e += 256) {
-        const int f = e >> 9, c = e & (NC - 1);
-        B12[f * 1728 + p12(c & 7, (c >> 3) & 7, c >> 6)] = Ul[e];
-    }
     const int32_t *gm = m.gmap + (size_t)leaf * NG;
-    for (int s = tid; s < NG; s += 256) {
-        const int pp = m.ghost_pad[s];
-        const int gi = pp % PB - GW, gj = (pp / PB) % PB - GW, gk = pp / (PB * PB) - GW;
-        if (gi < -2 || gi > 9 || gj < -2 || gj > 9 || gk < -2 || gk > 9) continue;
-        const int src = gm[s];
-        const int b = src >= 0 ? src : -src - 1;
-        const double *q = m.U + (size_t)(b >> 9) * LEAF_STRIDE + (b & (NC - 1));
-        for (int f = 0; f < NF; ++f) {
+    uint16_t *s = S[w];
+    const float *ys = (const float *)s;
+    double *vout = m.val + (size_t)leaf * NF * 26 * NSLOT;
+    for (int f = 0; f < NF; ++f) {
+        // gather field f: interior from U, the rest through the ghost map
+        // (skipping the outermost ghost layer, which no 3x3x3 neighbourhood of
+        // a needed cell reads)
+        for (int c = tid; c < NC; c += 256) B12[p12(c & 7, (c >> 3) & 7, c >> 6)] = Ul[f * NC + c];
+        for (int g = tid; g < NG; g += 256) {
+            const int pp = m.ghost_pad[g];
+            const int gi = pp % PB - GW, gj = (pp / PB) % PB - GW, gk = pp / (PB * PB) - GW;
+            if (gi < -2 || gi > 9 || gj < -2 || gj > 9 || gk < -2 || gk > 9) continue;
+            const int src = gm[g];
+            const int b = src >= 0 ? src : -src - 1;
+            const double *qf = m.U + (size_t)(b >> 9) * LEAF_STRIDE + f * NC + (b & (NC - 1));
             double v;
             if (src >= 0) {
-                v = q[f * NC];
+                v = qf[0];
             } else {
-                const double *qf = q + f * NC;
                 double acc = 0.0;
                 acc = acc + qf[0];
                 acc = acc + qf[1];
@@ -420,59 +530,76 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(MlpInfer m) {
                 acc = acc + qf[73];
                 v = acc * 0.125;
             }
-            B12[f * 1728 + p12(gi, gj, gk)] = v;
+            B12[p12(gi, gj, gk)] = v;
         }
-    }
-    __syncthreads();
-    uint16_t *s = S[w];
-    float *ys = (float *)s;
-    for (int chunk = w; chunk < (NSLOT + 8) / 9; chunk += 4) {
-        const int slot = 9 * chunk + lane / 7, f = lane - 7 * (lane / 7);
-        const bool live = lane < 63 && slot < NSLOT;
-        double nb[27], sigma = 0.0;
-        const int c12 = c_slot_cell[live ? slot : 0];
-        const double *q = B12 + f * 1728;
+        __syncthreads();
+        for (int chunk = w; chunk < NSLOT / 64; chunk += 4) {
+            const int slot = 64 * chunk + lane;
+            const int c12 = c_slot_cell[slot];
+            const double qc = B12[c12];
+            double sigma = 0.0;
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx)
-                    nb[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)] = q[c12 + dx + RB12 * dy + RB12 * RB12 * dz];
-        const double qc = nb[13];
-#pragma unroll
-        for (int o = 0; o < 27; ++o) {
-            const double a = fabs(nb[o] - qc);
-            sigma = a > sigma ? a : sigma;
-        }
-        const bool flat = !(sigma > 0.0);
-        const double rs = flat ? 0.0 : 1.0 / sigma;
-        for (int k = 0; k < 64; ++k) {
-            float v = 0.f;
-            if (k < 27) v = (float)((nb[k] - qc) * rs);
-            else if (k < IN) v = (k - 27 == f) ? 1.f : 0.f;
-            s[lane * LDA + k] = (live && !flat) ? bf16_bits(v) : (uint16_t)0;
-        }
-        forward64(s, m.wb, m.par, lane, nullptr, nullptr, nullptr, nullptr, 0, 0);
-        double val[26];
-#pragma unroll
-        for (int d = 0; d < 26; ++d) val[d] = flat ? qc : qc + sigma * (double)ys[lane * LDY + d];
-        if (!flat) limit_row(nb, val);
-        const bool ok = !live || flat || row_ok(nb, val, f);
-        const unsigned long long mask = __ballot(ok);
-        // count the cells that fall back to plain PPM (lane 7m holds cell m)
-        const bool cell_fails = live && f == 0 && ((mask >> (7 * (lane / 7))) & 0x7fu) != 0x7fu;
-        const unsigned long long fails = __ballot(cell_fails);
-        if (lane == 0 && fails) atomicAdd(m.fb_count, (unsigned long long)__popcll(fails));
-        if (live) {
-            const size_t row = ((size_t)leaf * NSLOT + slot) * NF + f;
-#pragma unroll
-            for (int d = 0; d < 26; ++d) m.val[row * 26 + d] = val[d];
-            if (f == 0) {
-                const unsigned bits = (unsigned)((mask >> (7 * (lane / 7))) & 0x7fu);
-                m.cell_ok[(size_t)leaf * NSLOT + slot] = bits == 0x7fu ? 1 : 0;
+            for (int o = 0; o < 27; ++o) {
+                const double a = fabs(B12[c12 + (o % 3 - 1) + RB12 * ((o / 3) % 3 - 1) +
+                                          RB12 * RB12 * (o / 9 - 1)] - qc);
+                sigma = a > sigma ? a : sigma;
             }
+            const bool flat = !(sigma > 0.0);
+            const double rs = flat ? 0.0 : 1.0 / sigma;
+            __builtin_amdgcn_sched_barrier(0);
+            // features in bf16, four per 8-byte store: 27 normalised
+            // neighbours, the one-hot field id, zeros up to K = 64
+#pragma unroll
+            for (int k4 = 0; k4 < 16; ++k4) {
+                uint64_t pack = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 4 * k4 + t;
+                    float v = 0.f;
+                    if (k < 27)
+                        v = (float)((B12[c12 + (k % 3 - 1) + RB12 * ((k / 3) % 3 - 1) +
+                                         RB12 * RB12 * (k / 9 - 1)] - qc) * rs);
+                    else if (k < IN)
+                        v = (k - 27 == f) ? 1.f : 0.f;
+                    const uint64_t bits = flat ? 0u : bf16_bits(v);
+                    pack |= bits << (16 * t);
+                }
+                *(uint64_t *)(s + lane * LDA + 4 * k4) = pack;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll 1
+            for (int mt = 0; mt < 4; ++mt) infer_tile(s, m.wb, m.par, lane, mt);
+            // line by line: denormalise, limit, check, store
+            const int lines[13] = {14, 16, 22, 17, 11, 23, 5, 25, 7, 26, 8, 20, 2};   // dir27 of +d
+            bool ok = true;
+#pragma unroll
+            for (int l = 0; l < 13; ++l) {
+                const int op = lines[l], om = 26 - op;
+                const int ip = op < 13 ? op : op - 1, im = om < 13 ? om : om - 1;
+                double R = qc, L = qc;
+                if (!flat) {
+                    R = qc + sigma * (double)ys[lane * LDY + ip];
+                    L = qc + sigma * (double)ys[lane * LDY + im];
+                    const double nbR = B12[c12 + (op % 3 - 1) + RB12 * ((op / 3) % 3 - 1) +
+                                           RB12 * RB12 * (op / 9 - 1)];
+                    const double nbL = B12[c12 + (om % 3 - 1) + RB12 * ((om / 3) % 3 - 1) +
+                                           RB12 * RB12 * (om / 9 - 1)];
+                    ok = limit_check_line(qc, nbR, nbL, f, R, L) && ok;
+                }
+                vout[(size_t)(f * 26 + ip) * NSLOT + slot] = R;
+                vout[(size_t)(f * 26 + im) * NSLOT + slot] = L;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (!ok) okc[slot] = 0;
         }
+        __syncthreads();   // B12 and okc complete before the next field
+    }
+    // verdicts, and the cells that fall back to plain PPM
+    for (int c = tid; c < NSLOT; c += 256) {   // trip count uniform per wave
+        const bool ok = okc[c] != 0;
+        m.cell_ok[(size_t)leaf * NSLOT + c] = ok ? 1 : 0;
+        const unsigned long long fails = __ballot(!ok);
+        if (lane == 0 && fails) atomicAdd(m.fb_count, (unsigned long long)__popcll(fails));
     }
 }
 

@@ -443,7 +443,8 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
 // Where a lane's point values come from: plain PPM, or (learned
 // reconstruction, cell passed the FP64 check) the inference pre-pass.
 struct ValSrc {
-    const double *val;     // [7][26] of this cell, or null for plain PPM
+    const double *val;     // this cell's values, (field f, dir d) at val[(26 f + d) * 896],
+                           // or null for plain PPM
 };
 
 __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
@@ -457,8 +458,8 @@ __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy
         const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            pos[f] = src.val[f * 26 + dp];
-            neg[f] = src.val[f * 26 + dm];
+            pos[f] = src.val[(size_t)(f * 26 + dp) * mlp::NSLOT];
+            neg[f] = src.val[(size_t)(f * 26 + dm) * mlp::NSLOT];
         }
     } else {
         line_ends(P, c, dx, dy, dz, pos, neg);
@@ -503,8 +504,9 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     const int cB = pidx(bi, bj, bk);
     ValSrc src{nullptr};
     if (a.mlp_val) {
-        const size_t row = (size_t)leaf * mlp::NSLOT + mlp::slot_of(bi, bj, bk);
-        if (a.mlp_ok[row]) src.val = a.mlp_val + row * NF * 26;
+        const int slot = mlp::slot_of(bi, bj, bk);
+        if (a.mlp_ok[(size_t)leaf * mlp::NSLOT + slot])
+            src.val = a.mlp_val + (size_t)leaf * NF * 26 * mlp::NSLOT + slot;
     }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;
