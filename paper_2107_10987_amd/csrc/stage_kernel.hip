@@ -37,6 +37,13 @@ __device__ __forceinline__ int pidx(int i, int j, int k) {
     return ((k + GW) * PB + (j + GW)) * PB + (i + GW);
 }
 
+// pow for the dual-energy switch at face points, which only fires where the
+// internal energy is a tiny fraction of the total, and for the tracer resync
+// (once per cell and step).  Kept out of line: inlined, its polynomial
+// constants are hoisted out of the walk's loops into registers for the whole
+// kernel and spilled (a scratch write stream of ~170 B per lane per launch).
+__device__ __attribute__((noinline)) double pow_cold(double x, double y) { return pow(x, y); }
+
 // Monotonised-central slope of the middle value (zero at an extremum).
 __device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     const double dl = q0 - qm;
@@ -111,7 +118,7 @@ __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double
     const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
-    if (eint < ph.eta1 * E) eint = pow(tau, ph.gamma);
+    if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
     {
 #pragma clang fp contract(fast)
         const double vn = (n == 0) ? v0 : ((n == 1) ? v1 : v2);
@@ -144,7 +151,7 @@ __device__ __forceinline__ double side_flux(const double U[NF], double xq, doubl
     const double un = (N == 0) ? (v0 + ph.omega * yq) : ((N == 1) ? (v1 - ph.omega * xq) : v2);
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
-    if (eint < ph.eta1 * E) eint = pow(tau, ph.gamma);
+    if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
     const double p = (ph.gamma - 1.0) * eint;
     const double cs = sqrt(ph.gamma * p * rinv);
     F[RHO] = rho * un;
@@ -308,7 +315,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
         const double rinv = 1.0 / o[RHO];
         const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
         const double eint = o[EGAS] - ek;
-        if (eint > a.ph.eta2 * o[EGAS]) o[TAU] = pow(eint, 1.0 / a.ph.gamma);
+        if (eint > a.ph.eta2 * o[EGAS]) o[TAU] = pow_cold(eint, 1.0 / a.ph.gamma);
     }
     bool bad = !(o[RHO] > 0.0);
     int badf = bad ? RHO : -1;
@@ -599,6 +606,39 @@ __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const 
     }
 }
 
+// One axis of a leaf with the differences accumulated in one workspace
+// slice W (linear cell index): the x pass writes, the y pass adds, and the z
+// pass adds and finishes the cell, summing as (x + y) + z like the
+// three-slice path.  The caller separates the passes with a workgroup
+// barrier (a cell belongs to different lanes in different passes).
+__device__ __forceinline__ void col_axis_accumulate(int N, const StageArgs &a, const double *P,
+                                                    const ColLane &L, int leaf, double *W,
+                                                    double &smax) {
+    const double dx = a.dx[leaf];
+    const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
+    double d[NF];
+    double sm = 0.0;
+    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
+    smax = L.live && sm > smax ? sm : smax;
+    if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
+        const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
+                    : (N == 1) ? (L.c2 * NX + L.cell) * NX + L.c1
+                               : (L.cell * NX + L.c2) * NX + L.c1;
+        if (N == 0) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) W[f * NC + c] = d[f];
+        } else if (N == 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) W[f * NC + c] = W[f * NC + c] + d[f];
+        } else {
+            double dsum[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) dsum[f] = W[f * NC + c] + d[f];
+            finish_cell(a, leaf, c, dx, stage_dt(a), dsum);
+        }
+    }
+}
+
 // The final pass of a leaf: sum the three axes' differences from W and
 // finish every interior cell.
 __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, const double *W,
@@ -626,13 +666,15 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
     double smax = 0.0;
 #pragma unroll 1
-    for (int n = 0; n < 3; ++n) col_axis_to_ws(n, a, P, L, leaf, W, smax);
+    for (int n = 0; n < 3; ++n) {
+        col_axis_accumulate(n, a, P, L, leaf, W, smax);
+        if (n < 2) __syncthreads();   // the slice's cells change owners between passes
+    }
     const double wm = wave_max(smax);
-    __syncthreads();  // the input block is dead; workspace writes are visible
+    __syncthreads();  // the input block is dead
     double *red = P;
     if (L.lane == 0) red[L.wave] = wm;
     __syncthreads();
-    col_finish_leaf(a, leaf, W, tid, NTC);
     if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
 }
 
@@ -659,16 +701,21 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
-        const int n0 = T == 1 ? 0 : tile, n1 = T == 1 ? 3 : tile + 1;
+        if (T == 1) {
 #pragma unroll 1
-        for (int n = n0; n < n1; ++n) col_axis_to_ws(n, a, P, L, leaf, W, smax);
+            for (int n = 0; n < 3; ++n) {
+                col_axis_accumulate(n, a, P, L, leaf, W, smax);
+                if (n < 2) __syncthreads();
+            }
+        } else {
+            col_axis_to_ws(tile, a, P, L, leaf, W, smax);
+        }
         const double wm = wave_max(smax);
         __syncthreads();
         double *red = P;
         if (L.lane == 0) red[L.wave] = wm;
         __syncthreads();
         if (T == 1) {
-            col_finish_leaf(a, leaf, W, tid, NTC);
             if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
         } else {
             if (tid == 0) {
