@@ -53,7 +53,54 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the polytrope plain/learned legs")
     ap.add_argument("--train-pairs", type=int, default=2 ** 20)
     ap.add_argument("--train-epochs", type=int, default=2)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the timed steps, one untimed device copy of this many MiB from a "
+                         "freshly written buffer (the reference kernel for HBM counter calibration)")
     return ap.parse_args()
+
+
+# HBM bytes per stage launch of the timed kernel, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs calibrated on a plain copy; valid only for the kernel
+# sources they were measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_col-sedov64-traffic.json")
+KERNEL_SOURCES = ("paper_2107_10987_amd/csrc/stage_kernel.hip", "paper_2107_10987_amd/csrc/hydro_common.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(schedule: str):
+    """Bytes per launch from the committed counter summary, or None when it
+    is missing, was taken on another schedule, or the kernel has changed."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("schedule") != schedule or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_probe(torch, mib: int):
+    """src -> dst device copy of `mib` MiB, with 512 MiB written in between
+    so that src is no longer in the caches (the 256 MB last-level cache
+    included) when the copy reads it."""
+    n = mib * 2 ** 20 // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    flush = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    flush.fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst, flush
 
 
 def cpu_baseline(w, budget_s: float):
@@ -153,6 +200,8 @@ def main():
     g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma)
 
     dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, args.copy_probe_mib)
 
     def run(nsteps, timed=False):
         # dt0 from the signal-speed pre-pass, then every step reads dt from
@@ -200,7 +249,8 @@ def main():
                    "schedule": args.schedule, "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
                    "kernel_cell_updates_per_s": cells_per_launch / avg_launch_s},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(args.schedule)},
         "hbm": {"achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / PEAK_HBM_GBS},
     }

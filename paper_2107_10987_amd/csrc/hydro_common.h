@@ -91,6 +91,19 @@ struct RefluxArgs {
 
 enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
 
+// Leaf (within a launch of n leaves, one workgroup each) of workgroup b.
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (b runs on
+// XCD b % 8), each with its own L2; XCD x gets a contiguous range of the
+// launch's leaves, which are in Morton order, so the ghost cells a workgroup
+// reads mostly belong to leaves its own L2 has just seen.  A bijection on
+// [0, n); every leaf's result is independent of which workgroup computes it.
+__device__ __forceinline__ int xcd_leaf(int b, int n) {
+    constexpr int NXCD = 8;
+    const int q = n / NXCD, r = n % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
 }  // namespace hydro
 
 // Launchers implemented in the kernel translation unit.

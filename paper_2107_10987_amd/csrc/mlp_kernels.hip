@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) m
     __shared__ double B12[RB12 * RB12 * RB12];           // 13,824 B
     __shared__ uint16_t S[4][STAGE_ELEMS];               // 34,816 B
     __shared__ uint8_t okc[NSLOT];
-    const int leaf = m.leaf0 + blockIdx.x;
+    const int leaf = m.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int c = tid; c < NSLOT; c += 256) okc[c] = 1;
     const double *Ul = m.U + (size_t)leaf * LEAF_STRIDE;

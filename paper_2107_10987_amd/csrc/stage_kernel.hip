@@ -353,7 +353,7 @@ __device__ __forceinline__ void store_amax(const StageArgs &a, int leaf, const d
 
 __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     __shared__ double P[NF * NP];
-    const int leaf = a.leaf0 + blockIdx.x;
+    const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
 
     gather_block(P, a.Uin, a.gmap, leaf, tid, NT);
@@ -658,7 +658,7 @@ __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, co
 // One leaf per workgroup, all three axes.
 __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
-    const int leaf = a.leaf0 + blockIdx.x;
+    const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     gather_block(P, a.Uin, a.gmap, leaf, tid, NTC);
     __syncthreads();
