@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--schedule", default="column", choices=["column", "face", "persistent", "tiled", "auto"])
-    ap.add_argument("--no-batched", action="store_true", help="skip the polytrope plain/learned legs")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the polytrope and binary plain/learned legs (and the network training)")
+    ap.add_argument("--no-binary", action="store_true", help="skip the 32768-leaf binary leg")
     ap.add_argument("--train-pairs", type=int, default=2 ** 20)
     ap.add_argument("--train-epochs", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -124,21 +126,82 @@ def cpu_baseline(w, budget_s: float):
                        f"({w.n} leaves, {threads} host threads, {el:.1f} s)")
 
 
-def batched_legs(torch, args):
+def train_network(torch, args):
+    from paper_2107_10987_amd import learned
+    t0 = time.perf_counter()
+    params, hist = learned.train_default(torch, n_pairs=args.train_pairs, epochs=args.train_epochs)
+    info = {"pairs": args.train_pairs, "epochs": args.train_epochs, "seconds": time.perf_counter() - t0,
+            "final_train_loss": hist[-1]["train_loss"], "val_loss": hist[-1]["val_loss"]}
+    return params, info
+
+
+def binary_leg(torch, args, params):
+    """The 32768-leaf binary star (16,777,216 cells, four levels), launched as
+    seeded uneven batches with autotuned schedules; 10 SSP-RK2 steps with the
+    time step on the device, captured in one HIP graph and replayed: plain PPM
+    and the learned reconstruction with FP64 check and plain-PPM fallback."""
+    from paper_2107_10987_amd.hydro import Hydro
+    from paper_2107_10987_amd.workloads import binary_star, uneven_batches
+
+    t0 = time.perf_counter()
+    w = binary_star()
+    build_s = time.perf_counter() - t0
+    off = uneven_batches(w.n)
+    U0 = torch.tensor(w.U, device="cuda")
+    nsteps = 10
+    out = {"workload": ("binary-32768: two n=1.5 polytropes (mass ratio 0.5, separation 0.5) on a "
+                        f"4-level octree of {w.n} leaves, co-rotating Omega {w.omega:.4f}, "
+                        f"{len(off) - 1} seeded uneven launches per stage, autotuned schedules, "
+                        f"{nsteps} steps in one HIP graph with the time step on the device"),
+           "host_build_seconds": build_s}
+    results = {}
+    for name, on in (("plain", False), ("learned", True)):
+        hy = Hydro(max_leaves=w.n, schedule="auto", learned=on)
+        try:
+            s = torch.cuda.Stream()
+            g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma, launch_off=off, stream=s)
+            if on:
+                hy.mlp_load(params)
+            torch.cuda.synchronize()
+            hy.autotune(g)
+            dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+            hy.dt(g, w.cfl, dt_dev)
+            hy.graph_capture(g, w.cfl, dt_dev, nsteps)
+            hy.graph_launch(s)            # untimed: the first 10 steps
+            s.synchronize()
+            if on:
+                hy.mlp_stats()            # reset the fallback counters
+            t1 = time.perf_counter()
+            hy.graph_launch(s)            # timed: steps 11..20
+            s.synchronize()
+            el = time.perf_counter() - t1
+            hy.check(s)
+            results[name] = g.U.cpu().numpy()
+            out[name] = {"value": w.cells * 2 * nsteps / el, "unit": "cell-updates/s",
+                         "ms_per_step": el / nsteps * 1e3, "launches_per_stage": len(off) - 1,
+                         "dt_after": float(dt_dev.item())}
+            if on:
+                cells, fb = hy.mlp_stats()
+                out[name]["fallback_fraction"] = fb / max(cells, 1)
+        finally:
+            hy.close()
+    d = np.abs(results["learned"] - results["plain"])
+    out["learned"]["l1_rel_dev_vs_plain"] = float(d.sum() / np.abs(results["plain"]).sum())
+    out["learned"]["gain_vs_plain"] = out["learned"]["value"] / out["plain"]["value"]
+    return out
+
+
+def batched_legs(torch, args, params):
     """The 4096-leaf rotating polytrope on a 3-level octree, launched as seeded
     uneven batches with autotuned schedules: one SSP-RK2 step (two stages) at
     the CFL time step, timed over repeats (median), plain PPM and the learned
     reconstruction with FP64 check and plain-PPM fallback."""
-    from paper_2107_10987_amd import learned
     from paper_2107_10987_amd.hydro import Hydro
     from paper_2107_10987_amd.workloads import rotating_polytrope, uneven_batches
 
     w = rotating_polytrope()
     off = uneven_batches(w.n)
     U0 = torch.tensor(w.U, device="cuda")
-    t0 = time.perf_counter()
-    params, hist = learned.train_default(torch, n_pairs=args.train_pairs, epochs=args.train_epochs)
-    train_s = time.perf_counter() - t0
     out = {}
     table = None
     results = {}
@@ -172,8 +235,6 @@ def batched_legs(torch, args):
     out["learned"]["l1_rel_dev_vs_plain"] = float(d.sum() / np.abs(results["plain"]).sum())
     out["learned"]["linf_rel_dev_vs_plain"] = float(d.max() / np.abs(results["plain"]).max())
     out["learned"]["gain_vs_plain"] = out["learned"]["value"] / out["plain"]["value"]
-    out["training"] = {"pairs": args.train_pairs, "epochs": args.train_epochs, "seconds": train_s,
-                       "final_train_loss": hist[-1]["train_loss"], "val_loss": hist[-1]["val_loss"]}
     out["workload"] = ("polytrope-4096: rotating n=1.5 polytrope, 3-level octree of 4096 leaves, "
                        f"Omega 0.1, {len(off) - 1} seeded uneven batches, autotuned schedules, dt at CFL 0.4")
     out["autotune_table"] = table
@@ -256,7 +317,11 @@ def main():
     }
     hy.close()
     if not args.no_batched:
-        out["batched"] = batched_legs(torch, args)
+        params, info = train_network(torch, args)
+        out["batched"] = batched_legs(torch, args, params)
+        out["batched"]["training"] = info
+        if not args.no_binary:
+            out["binary"] = binary_leg(torch, args, params)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -45,6 +45,7 @@ struct hydro_t {
     uint16_t *ghost_pad = nullptr; // [2232]
     unsigned long long *fb_count = nullptr;
     int64_t mlp_cells = 0;
+    int64_t graph_mlp_cells = 0;   // cells the captured graph reconstructs per replay
     std::vector<void *> mlp_bufs;  // everything allocated for the network
     double *amax = nullptr;    // per-leaf signal speeds [max_leaves]
     Status *status = nullptr;  // device status word
@@ -595,7 +596,10 @@ int hydro_graph_capture(hydro_t *h, const hydro_grid *g, double cfl, double *dt_
     if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+    const int64_t cells0 = h->mlp_cells;   // capture records launches, it runs none
     for (int k = 0; k < nsteps && rc == HYDRO_OK; ++k) rc = run_step_dev(h, g, cfl, dt_dev, false);
+    h->graph_mlp_cells = h->mlp_cells - cells0;
+    h->mlp_cells = cells0;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
@@ -612,7 +616,9 @@ int hydro_graph_launch(hydro_t *h, void *stream) {
     int rc = set_device(h);
     if (rc) return rc;
     hipError_t e = hipGraphLaunch(h->graph_exec, (hipStream_t)stream);
-    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "hipGraphLaunch");
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    h->mlp_cells += h->graph_mlp_cells;
+    return HYDRO_OK;
 }
 
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table) {
@@ -628,6 +634,7 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
     hydro_grid sub = *g;
     sub.n_launch = 0;
     sub.launch_off = nullptr;
+    sub.n_reflux = 0;   // timing launches over the first leaves only: no coarse/fine fix-up
     int best_prev = HYDRO_SCHED_COLUMN;
     for (int b = 0; b < HYDRO_NBUCKET && rc == HYDRO_OK; ++b) {
         const int size = 1 << b;

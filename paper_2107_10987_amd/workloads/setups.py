@@ -48,10 +48,17 @@ class Workload:
 def conserved_from_primitive(rho, vx, vy, vz, p, spc, gamma):
     """Stack (rho, s, E, tau, X) with E = p/(gamma-1) + rho|v|^2/2 and
     tau = (p/(gamma-1))**(1/gamma)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    U = np.empty((rho.shape[0], 7) + rho.shape[1:], dtype=np.float64)
     eint = p / (gamma - 1.0)
-    ek = 0.5 * rho * (vx * vx + vy * vy + vz * vz)
-    return np.stack([rho, rho * vx, rho * vy, rho * vz, eint + ek,
-                     eint ** (1.0 / gamma), spc], axis=1)
+    U[:, 0] = rho
+    np.multiply(rho, vx, out=U[:, 1])
+    np.multiply(rho, vy, out=U[:, 2])
+    np.multiply(rho, vz, out=U[:, 3])
+    U[:, 4] = eint + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    np.power(eint, 1.0 / gamma, out=U[:, 5])
+    U[:, 6] = spc
+    return U
 
 
 # --------------------------------------------------------------------------

@@ -238,3 +238,41 @@ def test_gain_report_polytrope(torch, trained):
     print(f"plain {rate_p:.3e} cell-updates/s, learned {rate_l:.3e} (x{rate_l / rate_p:.2f}); "
           f"fallback {fb}/{cells}; L1 rel deviation {l1:.2e}", flush=True)
     assert np.isfinite(Ul).all() and l1 < 1e-2
+
+
+def test_learned_graph_replay_matches_eager_and_counts_cells(torch, trained):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: learned path in a HIP graph (2 device-dt steps, 2 replays) vs eager, sedov-32^3", flush=True)
+    w = sedov_uniform(4)
+    eager = Hydro(max_leaves=w.n, schedule="column", learned=True)
+    graph = Hydro(max_leaves=w.n, schedule="column", learned=True)
+    try:
+        eager.mlp_load(trained)
+        graph.mlp_load(trained)
+        s = torch.cuda.Stream()
+        ge = eager.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        gg = graph.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, stream=s)
+        dte = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        eager.dt(ge, w.cfl, dte)
+        graph.dt(gg, w.cfl, dtg)
+        torch.cuda.synchronize()
+        graph.graph_capture(gg, w.cfl, dtg, 2)
+        torch.cuda.synchronize()
+        eager.mlp_stats()
+        assert graph.mlp_stats()[0] == 0          # capture runs nothing
+        for r in range(2):
+            for _ in range(2):
+                eager.step_dev(ge, w.cfl, dte)
+            graph.graph_launch(s)
+            torch.cuda.synchronize()
+            assert torch.equal(ge.U, gg.U), r
+            assert dte.item() == dtg.item(), r
+        ce, fe = eager.mlp_stats()
+        cg, fg = graph.mlp_stats()
+        assert ce == cg == 2 * 2 * 2 * w.n * 896
+        assert fe == fg
+    finally:
+        eager.close()
+        graph.close()
