@@ -255,12 +255,13 @@ def test_learned_graph_replay_matches_eager_and_counts_cells(torch, trained):
         dte = torch.zeros(1, dtype=torch.float64, device="cuda")
         dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        eager.dt(ge, w.cfl, dte)
+        eager.dt(ge, w.cfl, dte)                  # (the pre-pass reconstructs too)
         graph.dt(gg, w.cfl, dtg)
         torch.cuda.synchronize()
+        eager.mlp_stats()
+        graph.mlp_stats()
         graph.graph_capture(gg, w.cfl, dtg, 2)
         torch.cuda.synchronize()
-        eager.mlp_stats()
         assert graph.mlp_stats()[0] == 0          # capture runs nothing
         for r in range(2):
             for _ in range(2):
