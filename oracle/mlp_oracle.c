@@ -207,6 +207,18 @@ int oracle_mlp_features(const double *P, int i, int j, int k, int f, double nb[2
 int oracle_mlp_row_ok(const double nb[27], const double val[26], int f)
 {
     double qc = nb[13];
+    if (f == 0) {
+        /* the network's error is a few percent of sigma; where the density
+         * spans more than a factor 8 over the neighbourhood, the low side's
+         * point values (and the velocities s / rho formed from them) would
+         * carry relative errors of order one */
+        double lo = nb[0], hi = nb[0];
+        for (int o = 1; o < 27; ++o) {
+            if (nb[o] < lo) lo = nb[o];
+            if (nb[o] > hi) hi = nb[o];
+        }
+        if (!(hi <= 8.0 * lo)) return 0;
+    }
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {

@@ -135,6 +135,24 @@ def test_limiter_makes_predictions_pass_and_keeps_valid_rows(oracle_mod):
             assert oracle_mod.mlp_row_ok(nb, lim, f)
 
 
+def test_density_contrast_check(oracle_mod):
+    # values equal to the cell value pass bounds, positivity and monotonicity,
+    # so only the density-contrast criterion decides here
+    def row(lo, hi):
+        # 26 neighbours spread from lo to hi, the cell in the middle
+        nb = np.insert(np.linspace(lo, hi, 26), 13, 0.5 * (lo + hi))
+        return nb, np.full(26, nb[13])
+
+    nb, val = row(1.0, 8.0)               # max = 8 min exactly: passes
+    assert oracle_mod.mlp_row_ok(nb, val, 0)
+    nb, val = row(1.0, 8.0 * (1 + 2 ** -40))
+    assert not oracle_mod.mlp_row_ok(nb, val, 0)
+    for f in (1, 4, 5, 6):                # only the density row is tested
+        assert oracle_mod.mlp_row_ok(nb, val, f)
+    nb, val = row(1e-10, 1e-3)            # a star's edge against its atmosphere
+    assert not oracle_mod.mlp_row_ok(nb, val, 0)
+
+
 def test_nan_network_falls_back_everywhere_bitwise(oracle_mod):
     w = blast_single_leaf()
     p = _params(8)
