@@ -68,21 +68,26 @@ __device__ __forceinline__ void ppm_both(const double *q, int c, int st, double 
     const double sm = mc_slope(q0, q1, q2);
     const double s0 = mc_slope(q1, q2, q3);
     const double sp = mc_slope(q2, q3, q4);
-    double R = q2 + 0.5 * (q3 - q2) - (sp - s0) * sixth;
-    double L = q1 + 0.5 * (q2 - q1) - (s0 - sm) * sixth;
-    if ((R - q2) * (q2 - L) <= 0.0) {
-        L = q2;
-        R = q2;
-    } else {
-        const double D = R - L;
-        const double M6 = 6.0 * (q2 - 0.5 * (L + R));
-        if (D * M6 > D * D)
-            L = 3.0 * q2 - 2.0 * R;
-        else if (D * M6 < -(D * D))
-            R = 3.0 * q2 - 2.0 * L;
+    // the interface and constraint arithmetic may fuse multiply-adds (results
+    // within an ulp or two of the uncontracted expressions)
+    {
+#pragma clang fp contract(fast)
+        double R = q2 + 0.5 * (q3 - q2) - (sp - s0) * sixth;
+        double L = q1 + 0.5 * (q2 - q1) - (s0 - sm) * sixth;
+        if ((R - q2) * (q2 - L) <= 0.0) {
+            L = q2;
+            R = q2;
+        } else {
+            const double D = R - L;
+            const double M6 = 6.0 * (q2 - 0.5 * (L + R));
+            if (D * M6 > D * D)
+                L = 3.0 * q2 - 2.0 * R;
+            else if (D * M6 < -(D * D))
+                R = 3.0 * q2 - 2.0 * L;
+        }
+        left = L;
+        right = R;
     }
-    left = L;
-    right = R;
 }
 
 // Value at the +st end when `plus`, else at the -st end.
