@@ -9,18 +9,23 @@
  * face quadrature, flux divergence with rotating-frame sources, and a
  * two-stage SSP Runge-Kutta update with dual-energy (entropy tracer) pressure.
  *
+ * Leaves hold E^3 cells, E = 8 (default) or 16 (hydro_params.leaf_edge).  The
+ * kernels work on 8^3 tiles with three ghost layers (a 14^3 block in LDS); a
+ * 16^3 leaf is eight tiles, tile t at cell offset 8 (t & 1, (t >> 1) & 1, t >> 2).
+ *
  * Data layout (device memory owned by the caller unless noted):
- *   U         double [n][7][8][8][8]  fields rho, sx, sy, sz, E, tau, X per leaf;
+ *   U         double [n][7][E][E][E]  fields rho, sx, sy, sz, E, tau, X per leaf;
  *                                      cells [k][j][i], i fastest (structure of arrays)
  *   dx        double [n]               cell size of each leaf
  *   origin    double [n][3]            centre of cell (0,0,0) of each leaf; the frame
  *                                      rotates about the z axis through x = y = 0
- *   ghost_map int32  [n][2232]         source of every ghost cell of every leaf, in
- *                                      raster order (k, j, i in -3..10, i fastest,
- *                                      interior 0..7 skipped).  Entry s >= 0: copy
- *                                      cell s%512 of leaf s/512; s < 0: mean of the
- *                                      2x2x2 cells of leaf b/512 whose lowest cell is
- *                                      b%512, b = -s-1.  hydro_ghost_map builds it.
+ *   ghost_map int32  [n][T][2232]      T = (E/8)^3 tiles per leaf: source of every
+ *                                      ghost cell of every tile's 14^3 block, in raster
+ *                                      order (k, j, i in -3..10 relative to the tile,
+ *                                      i fastest, its 8^3 cells skipped).  Entry s >= 0:
+ *                                      copy cell s%E^3 of leaf s/E^3; s < 0: mean of the
+ *                                      2x2x2 cells of leaf b/E^3 whose lowest cell is
+ *                                      b%E^3, b = -s-1.  hydro_ghost_map builds it.
  * Every call is asynchronous on the caller's stream except where noted.
  * Return codes: 0 on success or a negative HYDRO_E* code; nothing aborts and no
  * C++ exception crosses this boundary.  A handle is not thread-safe; use one
@@ -74,7 +79,8 @@ typedef struct hydro_params {
                            section IV-B); same reconstruction                      */
     int32_t reflux;     /* 1: flux correction at coarse/fine faces (every grid then
                            carries face_flags and the reflux list from
-                           hydro_reflux_map); 0: none                              */
+                           hydro_reflux_map); 0: none.  8^3 leaves only.           */
+    int32_t leaf_edge;  /* cells per leaf edge: 8 (0 = 8) or 16                     */
 } hydro_params;
 
 /* One set of leaves that exchange ghosts: the whole mesh of a step. */
@@ -101,19 +107,20 @@ typedef struct hydro_tree {
     int32_t bc[3];          /* per axis: 0 periodic, 1 zero-gradient outflow         */
     const int32_t *level;   /* [n] refinement level of each leaf                     */
     const int32_t *coord;   /* [n][3] leaf coordinates at its level                  */
+    int32_t leaf_edge;      /* cells per leaf edge: 8 (0 = 8) or 16                  */
 } hydro_tree;
 
 /* Allocate every workspace the step needs (state copy for the first stage,
- * per-leaf flux differences of the column-walk schedule (86,016 B per leaf),
- * per-leaf signal speeds, error flags) for up to p->max_leaves leaves on
+ * per-tile flux differences of the column-walk schedule (86,016 B per 8^3
+ * tile), per-tile signal speeds, error flags) for up to p->max_leaves leaves on
  * p->device.  No later call allocates device memory.  *out is NULL on error. */
 int hydro_create(const hydro_params *p, hydro_t **out);
 
 /* Free the workspace; idempotent on NULL. */
 int hydro_destroy(hydro_t *h);
 
-/* Build the ghost map of a tree on the host into map[t->n][2232] (caller-owned
- * host memory).  Ghost cells take: periodic wrap or zero-gradient outflow at
+/* Build the ghost map of a tree on the host into map[t->n][T][2232] (caller-owned
+ * host memory; T = 1 for 8^3 leaves, 8 for 16^3 leaves).  Ghost cells take: periodic wrap or zero-gradient outflow at
  * the leaf's level; a same-level cell; the covering cell of a coarser leaf
  * (injection); or the mean of the 2x2x2 cells of a leaf one level finer.
  * Returns HYDRO_EINVAL if the tree is not 2:1 balanced or a leaf is outside
@@ -134,8 +141,9 @@ int hydro_ghost_map(const hydro_tree *t, int32_t *map);
  *     them: {leaf, mask of bits 0-5, child[6][4]}; child[f][o1 + 2 o2] is the
  *     finer leaf across face f whose offsets along the two other axes (in
  *     increasing axis order) are o1, o2; -1 for faces without finer leaves.
- * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face or a
- * leaf is outside the box.  Synchronous; needs no handle and no GPU. */
+ * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face, a
+ * leaf is outside the box, or the leaves are 16^3.  Synchronous; needs no
+ * handle and no GPU. */
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries);
 
 /* One full SSP Runge-Kutta step of all leaves, in place on g->U (Shu-Osher
@@ -165,7 +173,7 @@ int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax);
 
 /* Reconstructed values of every interior cell at its 26 points:
  * out (device [n][7][512][26]); point d = (dx,dy,dz) is numbered
- * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre. */
+ * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre.  8^3 leaves only. */
 int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out);
 
 /* One SSP-RK2 step driven on the device: both stages read dt from dt_dev
@@ -226,13 +234,14 @@ int hydro_mlp_train_step(hydro_t *h, const float *X, const float *T, int B, doub
 /* Training pairs from the plain reconstruction of g->U: rows
  * [leaf][cell][field] of the interior cells, X (device [n*3584][34]), the
  * plain PPM point values in the same normalisation T (device [n*3584][26]),
- * valid (device [n*3584], 0 where the neighbourhood is flat). */
+ * valid (device [n*3584], 0 where the neighbourhood is flat).  8^3 leaves only. */
 int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t *valid);
 /* Cells reconstructed by the learned path and cells that fell back to plain
  * PPM since the previous call (synchronises). */
 int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback);
 
-/* Device pointer to the per-leaf maximum signal speeds of the last step. */
+/* Device pointer to the maximum signal speeds of the last step, one per 8^3
+ * tile ([n] for 8^3 leaves, [n][8] for 16^3 leaves). */
 const double *hydro_amax_device(const hydro_t *h);
 
 /* Synchronise the handle's last stream and report HYDRO_ENONPHYS if any

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <fstream>
 #include <mutex>
 #include <sstream>
@@ -24,6 +25,7 @@ struct hydro_t {
     double *U1 = nullptr;      // first-stage state [max_leaves][7][512]
     double *U2 = nullptr;      // second-stage state of three-stage steps
     int rk = 2;
+    int ts = 0, lg = 3;        // 8^3 blocks per leaf (log2), leaf edge (log2)
     double *dscr = nullptr;    // column walk: [max_leaves][3][7][512]
     int *queue = nullptr;      // persistent launches: [2]
     int *leaf_done = nullptr;  // [max_leaves]
@@ -47,7 +49,7 @@ struct hydro_t {
     int64_t mlp_cells = 0;
     int64_t graph_mlp_cells = 0;   // cells the captured graph reconstructs per replay
     std::vector<void *> mlp_bufs;  // everything allocated for the network
-    double *amax = nullptr;    // per-leaf signal speeds [max_leaves]
+    double *amax = nullptr;    // per-block signal speeds [max_leaves << ts]
     Status *status = nullptr;  // device status word
     hipStream_t last_stream = nullptr;
     std::string err;
@@ -157,7 +159,10 @@ struct TreeIndex {
     int build(const hydro_tree *tree) {
         t = tree;
         if (!t || !t->level || !t->coord || t->n <= 0) return fail(nullptr, HYDRO_EINVAL, "null or empty tree");
-        if ((int64_t)t->n * NC > INT32_MAX) return fail(nullptr, HYDRO_EINVAL, "too many leaves for int32 cell ids");
+        if (t->leaf_edge != 0 && t->leaf_edge != 8 && t->leaf_edge != 16)
+            return fail(nullptr, HYDRO_EINVAL, "leaf_edge must be 8 or 16");
+        if ((int64_t)t->n * (t->leaf_edge == 16 ? 4096 : NC) > INT32_MAX)
+            return fail(nullptr, HYDRO_EINVAL, "too many leaves for int32 cell ids");
         for (int a = 0; a < 3; ++a)
             if (t->nb[a] <= 0 || (t->bc[a] != 0 && t->bc[a] != 1))
                 return fail(nullptr, HYDRO_EINVAL, "bad nb/bc");
@@ -248,6 +253,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.mlp_val = nullptr;
     a.mlp_ok = nullptr;
     a.centre_only = h->p.scheme == 1;
+    a.ts = h->ts;
+    a.lg = h->lg;
     const bool reflux = h->p.reflux && stage != 0;
     a.face_flags = reflux ? g->face_flags : nullptr;
     a.bflux = reflux ? h->bflux : nullptr;
@@ -255,8 +262,11 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
     for (int b = 0; b < nb; ++b) {
-        a.leaf0 = g->n_launch > 0 ? g->launch_off[b] : 0;
-        a.nleaf = g->n_launch > 0 ? g->launch_off[b + 1] - a.leaf0 : g->n;
+        // launches count 8^3 blocks: 2^ts per leaf
+        const int l0 = g->n_launch > 0 ? g->launch_off[b] : 0;
+        const int nl = g->n_launch > 0 ? g->launch_off[b + 1] - l0 : g->n;
+        a.leaf0 = l0 << h->ts;
+        a.nleaf = nl << h->ts;
         if (a.nleaf == 0) continue;
         set_schedule(a, resolve_schedule(h, a.nleaf));
         if (h->p.recon == 1) {
@@ -271,6 +281,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.cell_ok = h->mlp_ok;
             m.fb_count = h->fb_count;
             m.leaf0 = a.leaf0;
+            m.ts = h->ts;
+            m.lg = h->lg;
             hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, s);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
             h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
@@ -373,8 +385,14 @@ int run_stages(hydro_t *h, const hydro_grid *g, double dt, const double *dt_dev,
 int run_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, bool allow_timing) {
     int rc;
     if ((rc = run_stages(h, g, 0.0, dt_dev, allow_timing))) return rc;
-    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
+    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, h->ts, cfl, dt_dev, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
+}
+
+// Per-block signal speeds of the handle -> per-leaf values in out (device).
+int leaf_amax(hydro_t *h, const hydro_grid *g, double *out) {
+    hipError_t e = hydro_launch_amax_leaves(h->amax, h->ts, g->n, out, (hipStream_t)g->stream);
+    return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "amax reduction");
 }
 
 template <class T>
@@ -446,6 +464,12 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
         return fail(nullptr, HYDRO_EINVAL, "rk_order must be 2 or 3");
     if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, HYDRO_EINVAL, "scheme must be 0 or 1");
     if (p->reflux != 0 && p->reflux != 1) return fail(nullptr, HYDRO_EINVAL, "reflux must be 0 or 1");
+    if (p->leaf_edge != 0 && p->leaf_edge != 8 && p->leaf_edge != 16)
+        return fail(nullptr, HYDRO_EINVAL, "leaf_edge must be 8 or 16");
+    if (p->leaf_edge == 16 && p->reflux)
+        return fail(nullptr, HYDRO_EINVAL, "the coarse/fine flux correction supports 8^3 leaves only");
+    if ((int64_t)p->max_leaves * (p->leaf_edge == 16 ? 4096 : 512) > INT32_MAX)
+        return fail(nullptr, HYDRO_EINVAL, "max_leaves too large for int32 cell ids");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
         return fail(nullptr, HYDRO_EINVAL, "schedule must be one of HYDRO_SCHED_*");
     if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(nullptr, HYDRO_EINVAL, "eta1/eta2 must be >= 0");
@@ -454,6 +478,8 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     h->p = *p;
     h->device = p->device;
     h->rk = p->rk_order == 3 ? 3 : 2;
+    h->ts = p->leaf_edge == 16 ? 3 : 0;
+    h->lg = p->leaf_edge == 16 ? 4 : 3;
     int rc = set_device(h);
     if (rc) { g_create_err = h->err; delete h; return rc; }
     hipError_t e = ensure_ghost_table(h->device);
@@ -470,7 +496,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
         delete h;
         return rc;
     }
-    const size_t n = (size_t)p->max_leaves;
+    const size_t n = (size_t)p->max_leaves << h->ts;   // in 8^3 blocks
     e = hipMalloc((void **)&h->U1, n * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess && h->rk == 3) e = hipMalloc((void **)&h->U2, n * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->dscr, n * 3 * LEAF_STRIDE * sizeof(double));
@@ -526,8 +552,16 @@ int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out) {
     if ((rc = run_stages(h, g, dt, nullptr, true))) return rc;
     if (amax_out) {
         hipStream_t s = (hipStream_t)g->stream;
-        hipError_t e = hipMemcpyAsync(amax_out, h->amax, sizeof(double) * g->n, hipMemcpyDeviceToHost, s);
+        const size_t nb = (size_t)g->n << h->ts;
+        std::vector<double> blk(nb);
+        hipError_t e = hipMemcpyAsync(blk.data(), h->amax, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(h, e, "amax copy");
+        for (int l = 0; l < g->n; ++l) {
+            double m = blk[(size_t)l << h->ts];
+            for (int t = 1; t < (1 << h->ts); ++t) m = std::max(m, blk[((size_t)l << h->ts) + t]);
+            amax_out[l] = m;
+        }
         return read_status(h, s);
     }
     return HYDRO_OK;
@@ -544,7 +578,9 @@ int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const dou
     if (Uin == Uout) return fail(h, HYDRO_EINVAL, "Uout may not alias Uin");
     if (!(dt >= 0.0) || !isfinite(dt)) return fail(h, HYDRO_EINVAL, "dt must be finite and >= 0");
     if ((rc = set_device(h))) return rc;
-    return run_stage(h, g, stage, dt, Uin, stage >= 2 ? Un : Uin, Uout, amax, 0);
+    if (h->ts == 0) return run_stage(h, g, stage, dt, Uin, stage >= 2 ? Un : Uin, Uout, amax, 0);
+    if ((rc = run_stage(h, g, stage, dt, Uin, stage >= 2 ? Un : Uin, Uout, h->amax, 0))) return rc;
+    return amax ? leaf_amax(h, g, amax) : HYDRO_OK;
 }
 
 int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax) {
@@ -552,13 +588,16 @@ int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax) {
     if (rc) return rc;
     if (!g->U || !amax) return fail(h, HYDRO_EINVAL, "null U or amax");
     if ((rc = set_device(h))) return rc;
-    return run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, amax, 0, nullptr, false);
+    if (h->ts == 0) return run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, amax, 0, nullptr, false);
+    if ((rc = run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, h->amax, 0, nullptr, false))) return rc;
+    return leaf_amax(h, g, amax);
 }
 
 int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out) {
     int rc = check_grid(h, g);
     if (rc) return rc;
     if (!g->U || !out) return fail(h, HYDRO_EINVAL, "null U or out");
+    if (h->ts) return fail(h, HYDRO_EINVAL, "hydro_reconstruct supports 8^3 leaves only");
     if ((rc = set_device(h))) return rc;
     hipError_t e = hydro_launch_reconstruct(g->U, g->ghost_map, g->n, out, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "reconstruct launch");
@@ -580,7 +619,7 @@ int hydro_dt(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev) {
     if (!(cfl > 0.0) || !isfinite(cfl)) return fail(h, HYDRO_EINVAL, "cfl must be > 0");
     if ((rc = set_device(h))) return rc;
     if ((rc = run_stage(h, g, 0, 0.0, g->U, g->U, nullptr, h->amax, 0, nullptr, false))) return rc;
-    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, cfl, dt_dev, (hipStream_t)g->stream);
+    hipError_t e = hydro_launch_dt(g->dx, h->amax, g->n, h->ts, cfl, dt_dev, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "dt launch");
 }
 
@@ -751,6 +790,7 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
     int rc = check_grid(h, g);
     if (rc) return rc;
     if (!g->U || !X || !T || !valid) return fail(h, HYDRO_EINVAL, "null U or pair buffer");
+    if (h->ts) return fail(h, HYDRO_EINVAL, "hydro_mlp_pairs supports 8^3 leaves only");
     if ((rc = set_device(h))) return rc;
     hipError_t e = hydro_launch_pairs(g->U, g->ghost_map, g->n, X, T, valid, (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "pairs launch");
@@ -831,59 +871,71 @@ int hydro_ghost_map(const hydro_tree *t, int32_t *map) {
     int rc = ti.build(t);
     if (rc) return rc;
     const int lmax = ti.lmax;
-    auto find = [&](int l, const int64_t g[3]) -> int32_t { return ti.leaf(l, g[0] >> 3, g[1] >> 3, g[2] >> 3); };
-    auto local = [](const int64_t g[3]) -> int32_t {
-        return (int32_t)(((g[2] & 7) * NX + (g[1] & 7)) * NX + (g[0] & 7));
+    const int lg = t->leaf_edge == 16 ? 4 : 3;   // build() accepted 0, 8 or 16
+    const int64_t E = (int64_t)1 << lg;
+    const int tiles = t->leaf_edge == 16 ? 8 : 1;
+    // the leaf at level l holding global cell g (cells of that level), and
+    // the cell's index inside that leaf
+    auto find = [&](int l, const int64_t g[3]) -> int32_t { return ti.leaf(l, g[0] >> lg, g[1] >> lg, g[2] >> lg); };
+    auto local = [&](const int64_t g[3]) -> int32_t {
+        return (int32_t)((((g[2] & (E - 1)) * E + (g[1] & (E - 1))) * E) + (g[0] & (E - 1)));
     };
+    const int32_t cells = (int32_t)(E * E * E);
     for (int i = 0; i < t->n; ++i) {
         const int l = t->level[i];
         const int32_t *c = t->coord + 3 * (size_t)i;
-        int32_t *m = map + (size_t)i * NG;
-        int s = 0;
-        for (int k = -GW; k < NX + GW; ++k)
-            for (int j = -GW; j < NX + GW; ++j)
-                for (int ii = -GW; ii < NX + GW; ++ii) {
-                    if (ii >= 0 && ii < NX && j >= 0 && j < NX && k >= 0 && k < NX) continue;
-                    const int off[3] = {ii, j, k};
-                    int64_t g[3];
-                    for (int a = 0; a < 3; ++a) {
-                        const int64_t nc = (int64_t)NX * t->nb[a] << l;
-                        int64_t v = (int64_t)NX * c[a] + off[a];
-                        if (v < 0 || v >= nc) {
-                            if (t->bc[a] == 0) v = ((v % nc) + nc) % nc;
-                            else v = v < 0 ? 0 : nc - 1;
+        for (int tile = 0; tile < tiles; ++tile) {
+            const int to[3] = {8 * (tile & 1), 8 * ((tile >> 1) & 1), 8 * (tile >> 2)};
+            int32_t *m = map + ((size_t)i * tiles + tile) * NG;
+            int s = 0;
+            for (int k = -GW; k < NX + GW; ++k)
+                for (int j = -GW; j < NX + GW; ++j)
+                    for (int ii = -GW; ii < NX + GW; ++ii) {
+                        if (ii >= 0 && ii < NX && j >= 0 && j < NX && k >= 0 && k < NX) continue;
+                        const int off[3] = {ii, j, k};
+                        int64_t g[3];
+                        for (int a = 0; a < 3; ++a) {
+                            const int64_t nc = E * t->nb[a] << l;
+                            int64_t v = E * c[a] + to[a] + off[a];
+                            if (v < 0 || v >= nc) {
+                                if (t->bc[a] == 0) v = ((v % nc) + nc) % nc;
+                                else v = v < 0 ? 0 : nc - 1;
+                            }
+                            g[a] = v;
                         }
-                        g[a] = v;
-                    }
-                    int32_t src = -1;
-                    bool found = false;
-                    // a leaf at this level or coarser covering the cell
-                    for (int lc = l; lc >= 0 && !found; --lc) {
-                        const int64_t gc[3] = {g[0] >> (l - lc), g[1] >> (l - lc), g[2] >> (l - lc)};
-                        const int32_t o = find(lc, gc);
-                        if (o >= 0) {
-                            src = o * NC + local(gc);
-                            found = true;
+                        int32_t src = -1;
+                        bool found = false;
+                        // a leaf at this level or coarser covering the cell (the
+                        // leaf itself for cells of its other tiles)
+                        for (int lc = l; lc >= 0 && !found; --lc) {
+                            const int64_t gc[3] = {g[0] >> (l - lc), g[1] >> (l - lc), g[2] >> (l - lc)};
+                            const int32_t o = find(lc, gc);
+                            if (o >= 0) {
+                                src = o * cells + local(gc);
+                                found = true;
+                            }
                         }
+                        if (!found) {
+                            // refined: its 2x2x2 children must belong to one leaf of level l+1
+                            const int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
+                            const int32_t o = (l < lmax) ? find(l + 1, gf) : -1;
+                            if (o < 0)
+                                return fail(nullptr, HYDRO_EINVAL,
+                                            "ghost cell of leaf " + std::to_string(i) +
+                                                " is neither covered nor refined once (tree not 2:1 balanced)");
+                            src = -(o * cells + local(gf)) - 1;
+                        }
+                        m[s++] = src;
                     }
-                    if (!found) {
-                        // refined: its 2x2x2 children must belong to one leaf of level l+1
-                        const int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
-                        const int32_t o = (l < lmax) ? find(l + 1, gf) : -1;
-                        if (o < 0)
-                            return fail(nullptr, HYDRO_EINVAL,
-                                        "ghost cell of leaf " + std::to_string(i) +
-                                            " is neither covered nor refined once (tree not 2:1 balanced)");
-                        src = -(o * NC + local(gf)) - 1;
-                    }
-                    m[s++] = src;
-                }
+        }
     }
     return HYDRO_OK;
 }
 
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries) {
     if (!face_flags || !entries || !n_entries) return fail(nullptr, HYDRO_EINVAL, "null output");
+    if (t && t->leaf_edge == 16)
+        return fail(nullptr, HYDRO_EINVAL, "the coarse/fine flux correction supports 8^3 leaves only");
     TreeIndex ti;
     int rc = ti.build(t);
     if (rc) return rc;

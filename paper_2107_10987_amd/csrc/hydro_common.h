@@ -67,7 +67,31 @@ struct StageArgs {
     // flux correction at coarse/fine faces (null: none)
     const int32_t *face_flags;  // [n]: bits 0-5 corrected faces, 8-13 faces kept for a coarser leaf
     double *bflux;              // [n][6][7][64] Simpson flux of flagged boundary faces
+    // leaf edge E = 1 << lg cells (8 or 16); kernels work on 8^3 blocks, 1 << ts per leaf
+    int ts, lg;
 };
+
+// Leaves of E = 2^lg cells per edge (8 or 16) are processed as (E/8)^3 tiles
+// of 8^3 cells ("blocks"): block b is tile t = b mod 2^ts of leaf b >> ts, at
+// cell offset 8 (t & 1, (t >> 1) & 1, t >> 2) inside the leaf.  Everything a
+// kernel keeps per unit of work (ghost map, workspace, signal speed, learned
+// values) is per block; U, dx and origin are per leaf.  For 8^3 leaves
+// (ts = 0, lg = 3) a block is a leaf.
+__device__ __forceinline__ size_t block_base(int b, int ts, int lg) {
+    const int leaf = b >> ts, t = b & ((1 << ts) - 1);
+    const size_t E = (size_t)1 << lg;
+    return ((size_t)leaf * NF << (3 * lg)) +
+           ((size_t)(8 * (t >> 2)) * E + (size_t)(8 * ((t >> 1) & 1))) * E + (size_t)(8 * (t & 1));
+}
+// Offset from the block's base of its cell c = (k * 8 + j) * 8 + i.
+__device__ __forceinline__ int block_cell(int c, int lg) {
+    return ((c >> 6) << (2 * lg)) + (((c >> 3) & 7) << lg) + (c & 7);
+}
+// U offset (field 0) of the cell a ghost-map entry names, s = leaf E^3 + cell.
+__device__ __forceinline__ size_t src_offset(int s, int lg) {
+    const int sh = 3 * lg;
+    return ((size_t)(s >> sh) * NF << sh) + (size_t)(s & ((1 << sh) - 1));
+}
 
 // Boundary faces of a leaf: f = 2 axis + side (side 1 = +axis); the 64 face
 // cells of a face by (t1, t2) = the two other axes in increasing order,
@@ -110,8 +134,9 @@ __device__ __forceinline__ int xcd_leaf(int b, int n) {
 hipError_t hydro_upload_ghost_table(const uint16_t *table);
 hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
 hipError_t hydro_launch_reflux(const hydro::RefluxArgs &r, int n_entries, hipStream_t s);
-hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
-                           hipStream_t s);
+hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, int ts, double cfl,
+                           double *dt_out, hipStream_t s);
+hipError_t hydro_launch_amax_leaves(const double *blk, int ts, int n, double *out, hipStream_t s);
 hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,
                               uint8_t *valid, hipStream_t s);
 hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,

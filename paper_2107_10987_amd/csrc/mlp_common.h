@@ -38,15 +38,16 @@ struct MlpTrain {
 };
 
 struct MlpInfer {
-    const double *U;            // [n][7][512]
-    const int32_t *gmap;        // [n][2232]
+    const double *U;            // [n][7][E^3]
+    const int32_t *gmap;        // [blocks][2232]
     const uint16_t *ghost_pad;  // [2232] padded index of each ghost slot
     const uint16_t *wb;         // bf16 weights
     const float *par;           // float32 parameters (biases)
-    double *val;                // [n][7][26][896] limited point values (field, dir, slot)
-    uint8_t *cell_ok;           // [n][896]
+    double *val;                // [blocks][7][26][896] limited point values (field, dir, slot)
+    uint8_t *cell_ok;           // [blocks][896]
     unsigned long long *fb_count;  // cells that fell back to plain PPM
-    int leaf0;
+    int leaf0;                  // first block of the launch
+    int ts, lg;                 // blocks per leaf (log2), leaf edge (log2)
 };
 
 }  // namespace mlp

@@ -438,7 +438,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) m
     const int leaf = m.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int c = tid; c < NSLOT; c += 256) okc[c] = 1;
-    const double *Ul = m.U + (size_t)leaf * LEAF_STRIDE;
+    const double *Ub = m.U + block_base(leaf, m.ts, m.lg);   // leaf: the block
+    const size_t fs = (size_t)1 << (3 * m.lg);
+    const int E = 1 << m.lg, E2 = E * E;
     const int32_t *gm = m.gmap + (size_t)leaf * NG;
     uint16_t *s = S[w];
     const float *ys = (const float *)s;
@@ -447,14 +449,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) m
         // gather field f: interior from U, the rest through the ghost map
         // (skipping the outermost ghost layer, which no 3x3x3 neighbourhood of
         // a needed cell reads)
-        for (int c = tid; c < NC; c += 256) B12[p12(c & 7, (c >> 3) & 7, c >> 6)] = Ul[f * NC + c];
+        for (int c = tid; c < NC; c += 256) B12[p12(c & 7, (c >> 3) & 7, c >> 6)] = Ub[f * fs + block_cell(c, m.lg)];
         for (int g = tid; g < NG; g += 256) {
             const int pp = m.ghost_pad[g];
             const int gi = pp % PB - GW, gj = (pp / PB) % PB - GW, gk = pp / (PB * PB) - GW;
             if (gi < -2 || gi > 9 || gj < -2 || gj > 9 || gk < -2 || gk > 9) continue;
             const int src = gm[g];
             const int b = src >= 0 ? src : -src - 1;
-            const double *qf = m.U + (size_t)(b >> 9) * LEAF_STRIDE + f * NC + (b & (NC - 1));
+            const double *qf = m.U + src_offset(b, m.lg) + f * fs;
             double v;
             if (src >= 0) {
                 v = qf[0];
@@ -462,12 +464,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) m
                 double acc = 0.0;
                 acc = acc + qf[0];
                 acc = acc + qf[1];
-                acc = acc + qf[8];
-                acc = acc + qf[9];
-                acc = acc + qf[64];
-                acc = acc + qf[65];
-                acc = acc + qf[72];
-                acc = acc + qf[73];
+                acc = acc + qf[E];
+                acc = acc + qf[E + 1];
+                acc = acc + qf[E2];
+                acc = acc + qf[E2 + 1];
+                acc = acc + qf[E2 + E];
+                acc = acc + qf[E2 + E + 1];
                 v = acc * 0.125;
             }
             B12[p12(gi, gj, gk)] = v;

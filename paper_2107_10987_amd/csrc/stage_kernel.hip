@@ -231,41 +231,54 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Ghost-padded block of one leaf into LDS (nt threads cooperate).
-__device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm,
-                                             int leaf, int tid, int nt) {
-    const double *Ul = U + (size_t)leaf * LEAF_STRIDE;
+// Ghost-padded 14^3 block of block b into LDS (nt threads cooperate): its
+// 8^3 cells from U, its ghost cells through the ghost map (a copy, or the mean
+// of the 2x2x2 cells of a finer leaf, summed in z, y, x order).
+__device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm, int b,
+                                             int ts, int lg, int tid, int nt) {
+    const double *Ub = U + block_base(b, ts, lg);
+    const size_t fs = (size_t)1 << (3 * lg);
     for (int e = tid; e < LEAF_STRIDE; e += nt) {
         const int f = e >> 9, c = e & (NC - 1);
-        P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = Ul[e];
+        P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = Ub[f * fs + block_cell(c, lg)];
     }
-    const int32_t *g = gm + (size_t)leaf * NG;
+    const int32_t *g = gm + (size_t)b * NG;
+    const int E = 1 << lg, E2 = E * E;
     for (int s = tid; s < NG; s += nt) {
         const int src = g[s];
         const int p = c_ghost_pad[s];
         if (src >= 0) {
-            const double *q = U + (size_t)(src >> 9) * LEAF_STRIDE + (src & (NC - 1));
+            const double *q = U + src_offset(src, lg);
 #pragma unroll
-            for (int f = 0; f < NF; ++f) P[f * NP + p] = q[f * NC];
+            for (int f = 0; f < NF; ++f) P[f * NP + p] = q[f * fs];
         } else {
-            const int b = -src - 1;
-            const double *q = U + (size_t)(b >> 9) * LEAF_STRIDE + (b & (NC - 1));
+            const double *q = U + src_offset(-src - 1, lg);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const double *qf = q + f * NC;
+                const double *qf = q + f * fs;
                 double acc = 0.0;
                 acc = acc + qf[0];
                 acc = acc + qf[1];
-                acc = acc + qf[8];
-                acc = acc + qf[9];
-                acc = acc + qf[64];
-                acc = acc + qf[65];
-                acc = acc + qf[72];
-                acc = acc + qf[73];
+                acc = acc + qf[E];
+                acc = acc + qf[E + 1];
+                acc = acc + qf[E2];
+                acc = acc + qf[E2 + 1];
+                acc = acc + qf[E2 + E];
+                acc = acc + qf[E2 + E + 1];
                 P[f * NP + p] = acc * 0.125;
             }
         }
     }
+}
+
+// Cell size and centre of cell (0,0,0) of block b.
+__device__ __forceinline__ void block_geometry(const StageArgs &a, int b, double &dx, double &ox,
+                                               double &oy, double &oz) {
+    const int leaf = b >> a.ts, t = b & ((1 << a.ts) - 1);
+    dx = a.dx[leaf];
+    ox = a.origin[3 * leaf] + (double)(8 * (t & 1)) * dx;
+    oy = a.origin[3 * leaf + 1] + (double)(8 * ((t >> 1) & 1)) * dx;
+    oz = a.origin[3 * leaf + 2] + (double)(8 * (t >> 2)) * dx;
 }
 
 // Whether interior cell c lies on one of the faces set in mask (bit
@@ -293,13 +306,15 @@ __device__ __forceinline__ void store_bflux(const StageArgs &a, int leaf, int n,
 // of one interior cell; non-physical results are reported in a.status.
 __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c, double dx,
                                             double dt, const double dsum[NF]) {
+    // leaf: the block; its cell c lives at base in U, fields fs apart
     const double idx = 1.0 / dx;
-    const size_t base = (size_t)leaf * LEAF_STRIDE + c;
+    const size_t base = block_base(leaf, a.ts, a.lg) + block_cell(c, a.lg);
+    const size_t fs = (size_t)1 << (3 * a.lg);
     double u[NF], L[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         L[f] = -dsum[f] * idx;
-        u[f] = a.Uin[base + (size_t)f * NC];
+        u[f] = a.Uin[base + f * fs];
     }
     // rotating-frame source -Omega x s
     L[SX] = L[SX] + a.ph.omega * u[SY];
@@ -310,7 +325,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
         for (int f = 0; f < NF; ++f) o[f] = u[f] + dt * L[f];
     } else {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) o[f] = a.ca * a.Un[base + (size_t)f * NC] + a.cb * (u[f] + dt * L[f]);
+        for (int f = 0; f < NF; ++f) o[f] = a.ca * a.Un[base + f * fs] + a.cb * (u[f] + dt * L[f]);
     }
     // cells on a face the coarse/fine correction changes get their resync
     // after the correction, in the reflux pass
@@ -326,15 +341,16 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
     int badf = bad ? RHO : -1;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        a.Uout[base + (size_t)f * NC] = o[f];
+        a.Uout[base + f * fs] = o[f];
         if (!isfinite(o[f]) && !bad) {
             bad = true;
             badf = f;
         }
     }
     if (bad && atomicCAS(&a.status->flag, 0, 1) == 0) {
-        a.status->leaf = leaf;
-        a.status->cell = c;
+        const int lf = leaf >> a.ts;
+        a.status->leaf = lf;
+        a.status->cell = (int)(base - ((size_t)lf * NF << (3 * a.lg)));   // index within the leaf
         a.status->field = badf;
     }
 }
@@ -361,11 +377,11 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
 
-    gather_block(P, a.Uin, a.gmap, leaf, tid, NT);
+    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NT);
     __syncthreads();
 
-    const double dx = a.dx[leaf];
-    const double org[3] = {a.origin[3 * leaf], a.origin[3 * leaf + 1], a.origin[3 * leaf + 2]};
+    double dx, org[3];
+    block_geometry(a, leaf, dx, org[0], org[1], org[2]);
     double F0[NF], F1[NF], F2[NF];
     double smax = 0.0;
     face_flux<0>(P, tid, dx, org, a.ph, a.centre_only, F0, smax);
@@ -596,8 +612,8 @@ struct ColLane {
 // (linear cell index); returns this lane's signal speed maximum.
 __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const double *P,
                                                const ColLane &L, int leaf, double *W, double &smax) {
-    const double dx = a.dx[leaf];
-    const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
+    double dx, ox, oy, oz;
+    block_geometry(a, leaf, dx, ox, oy, oz);
     double d[NF];
     double sm = 0.0;
     column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
@@ -619,8 +635,8 @@ __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const 
 __device__ __forceinline__ void col_axis_accumulate(int N, const StageArgs &a, const double *P,
                                                     const ColLane &L, int leaf, double *W,
                                                     double &smax) {
-    const double dx = a.dx[leaf];
-    const double ox = a.origin[3 * leaf], oy = a.origin[3 * leaf + 1], oz = a.origin[3 * leaf + 2];
+    double dx, ox, oy, oz;
+    block_geometry(a, leaf, dx, ox, oy, oz);
     double d[NF];
     double sm = 0.0;
     column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
@@ -649,7 +665,7 @@ __device__ __forceinline__ void col_axis_accumulate(int N, const StageArgs &a, c
 __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, const double *W,
                                                 int tid, int nt) {
     if (a.stage == 0) return;
-    const double dx = a.dx[leaf];
+    const double dx = a.dx[leaf >> a.ts];
     const double dt = stage_dt(a);
     for (int c = tid; c < NC; c += nt) {
         double dsum[NF];
@@ -665,7 +681,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
-    gather_block(P, a.Uin, a.gmap, leaf, tid, NTC);
+    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NTC);
     __syncthreads();
     const ColLane L(tid);
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
@@ -702,7 +718,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         if (item >= items) break;
         const int leaf = a.leaf0 + item / T;
         const int tile = item - (item / T) * T;
-        gather_block(P, a.Uin, a.gmap, leaf, tid, NTC);
+        gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NTC);
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
@@ -833,7 +849,7 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(const double *U, const 
                                                          double *out) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, threadIdx.x, NT);
+    gather_block(P, U, gm, leaf, 0, 3, threadIdx.x, NT);
     __syncthreads();
     double *o = out + (size_t)leaf * NF * NC * 26;
     for (int e = threadIdx.x; e < NC * 26; e += NT) {
@@ -881,7 +897,7 @@ __global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_
                                                    float *T, uint8_t *valid) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, threadIdx.x, NT);
+    gather_block(P, U, gm, leaf, 0, 3, threadIdx.x, NT);
     __syncthreads();
     for (int e = threadIdx.x; e < NC * NF; e += NT) {
         const int c = e / NF, f = e - (e / NF) * NF;
@@ -923,12 +939,14 @@ hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *
 }
 
 // dt_out = cfl * min over leaves of dx / amax (one workgroup).
-__global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double *amax, int n,
+// dt = cfl * min over blocks of dx / a_max (blocks b of leaf b >> ts).
+__global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double *amax, int n, int ts,
                                                  double cfl, double *dt_out) {
     __shared__ double red[4];
     double m = INFINITY;
-    for (int l = threadIdx.x; l < n; l += 256) {
-        const double v = dx[l] / amax[l];
+    const int nb = n << ts;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const double v = dx[b >> ts] / amax[b];
         m = v < m ? v : m;
     }
 #pragma unroll
@@ -951,9 +969,27 @@ hipError_t hydro_launch_reflux(const RefluxArgs &r, int n_entries, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, double cfl, double *dt_out,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, dx, amax, n, cfl, dt_out);
+hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, int ts, double cfl,
+                           double *dt_out, hipStream_t s) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, dx, amax, n, ts, cfl, dt_out);
+    return hipGetLastError();
+}
+
+// Per-leaf maximum of the signal speeds of its 2^ts blocks.
+__global__ void __launch_bounds__(256) amax_leaves_kernel(const double *blk, int ts, int n, double *out) {
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= n) return;
+    double m = blk[(size_t)l << ts];
+    for (int t = 1; t < (1 << ts); ++t) {
+        const double v = blk[((size_t)l << ts) + t];
+        m = v > m ? v : m;
+    }
+    out[l] = m;
+}
+
+hipError_t hydro_launch_amax_leaves(const double *blk, int ts, int n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(amax_leaves_kernel, dim3((n + 255) / 256), dim3(256), 0, s, blk, ts, n, out);
     return hipGetLastError();
 }
 

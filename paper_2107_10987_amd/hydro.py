@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [("max_leaves", C.c_int32), ("device", C.c_int32), ("recon", C.c_int32),
                 ("schedule", C.c_int32), ("eta1", C.c_double), ("eta2", C.c_double),
                 ("tune_cache", C.c_char_p), ("mlp_batch", C.c_int32), ("rk_order", C.c_int32),
-                ("scheme", C.c_int32), ("reflux", C.c_int32)]
+                ("scheme", C.c_int32), ("reflux", C.c_int32), ("leaf_edge", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -52,7 +52,8 @@ class Grid(C.Structure):
 
 class Tree(C.Structure):
     _fields_ = [("n", C.c_int32), ("nb", C.c_int32 * 3), ("bc", C.c_int32 * 3),
-                ("level", C.POINTER(C.c_int32)), ("coord", C.POINTER(C.c_int32))]
+                ("level", C.POINTER(C.c_int32)), ("coord", C.POINTER(C.c_int32)),
+                ("leaf_edge", C.c_int32)]
 
 
 _lib = None
@@ -111,15 +112,17 @@ def _tree_struct(tree):
     a = tree.arrays()
     t = Tree(tree.n, (C.c_int32 * 3)(*a["nb"]), (C.c_int32 * 3)(*a["bc"]),
              a["level"].ctypes.data_as(C.POINTER(C.c_int32)),
-             a["coord"].ctypes.data_as(C.POINTER(C.c_int32)))
+             a["coord"].ctypes.data_as(C.POINTER(C.c_int32)), int(a["leaf_edge"]))
     return t, a
 
 
 def ghost_map(tree) -> np.ndarray:
-    """Ghost map int32 [n][2232] of a workloads.Tree, built by the library."""
+    """Ghost map of a workloads.Tree, built by the library: int32 [n][2232] for
+    8^3 leaves, [n][8][2232] (one map per 8^3 tile) for 16^3 leaves."""
     L = load()
     t, _keep = _tree_struct(tree)
-    out = np.empty((tree.n, NGHOST), dtype=np.int32)
+    shape = (tree.n, NGHOST) if tree.leaf_edge == NX else (tree.n, 8, NGHOST)
+    out = np.empty(shape, dtype=np.int32)
     rc = L.hydro_ghost_map(C.byref(t), out.ctypes.data_as(C.POINTER(C.c_int32)))
     if rc:
         raise HydroError(rc, L.hydro_last_error(None).decode())
@@ -155,7 +158,7 @@ class Hydro:
     def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
                  schedule: str = "auto", tune_cache: str | None = None, learned: bool = False,
                  mlp_batch: int = 4096, rk_order: int = 2, centre_only: bool = False,
-                 reflux: bool = False):
+                 reflux: bool = False, leaf_edge: int = NX):
         import torch
         self.torch = torch
         self.L = load()
@@ -163,9 +166,11 @@ class Hydro:
         self.schedule = schedule
         self.learned = learned
         self.reflux = reflux
+        self.leaf_edge = int(leaf_edge)
         self.p = Params(int(max_leaves), int(device), int(bool(learned)), SCHEDULES[schedule],
                         float(eta1), float(eta2), tune_cache.encode() if tune_cache else None,
-                        int(mlp_batch), int(rk_order), int(bool(centre_only)), int(bool(reflux)))
+                        int(mlp_batch), int(rk_order), int(bool(centre_only)), int(bool(reflux)),
+                        int(leaf_edge))
         h = C.c_void_p()
         rc = self.L.hydro_create(C.byref(self.p), C.byref(h))
         if rc:
@@ -297,8 +302,11 @@ class DeviceGrid:
         a = tree.arrays()
         self.n = tree.n
         self.U = U if isinstance(U, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(U), device=dev)
+        E = tree.leaf_edge
+        if E != hy.leaf_edge:
+            raise ValueError(f"tree has {E}^3 leaves, the handle {hy.leaf_edge}^3")
         assert self.U.dtype == torch.float64 and self.U.is_contiguous()
-        assert tuple(self.U.shape) == (tree.n, NF, NX, NX, NX)
+        assert tuple(self.U.shape) == (tree.n, NF, E, E, E)
         self.dx = torch.as_tensor(a["dx"], device=dev)
         self.origin = torch.as_tensor(a["origin"], device=dev)
         gm = ghost_map(tree) if gmap is None else gmap

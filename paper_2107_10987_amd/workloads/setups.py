@@ -42,7 +42,7 @@ class Workload:
 
     @property
     def cells(self) -> int:
-        return self.tree.n * NX ** 3
+        return self.tree.n * self.tree.leaf_edge ** 3
 
 
 def conserved_from_primitive(rho, vx, vy, vz, p, spc, gamma):
@@ -88,23 +88,25 @@ def blast_single_leaf(seed: int = 0, gamma: float = GAMMA) -> Workload:
 # Sedov-Taylor blast on a uniform grid of leaves
 # --------------------------------------------------------------------------
 def sedov_uniform(leaves_per_axis: int = 8, gamma: float = GAMMA, e_blast: float = 1.0,
-                  p_amb: float = 1e-5, rho_amb: float = 1.0) -> Workload:
-    """Uniform (8 m)^3 grid on [-1/2, 1/2]^3 as m^3 leaves with outflow faces.
+                  p_amb: float = 1e-5, rho_amb: float = 1.0, leaf_edge: int = NX) -> Workload:
+    """Uniform (E m)^3 grid on [-1/2, 1/2]^3 as m^3 leaves of E^3 cells
+    (E = leaf_edge, 8 or 16) with outflow faces.
 
     rho = 1, v = 0, p = 1e-5, and an energy ``e_blast`` deposited uniformly in
     the 2^3 cells around the box centre.  X = rho.
     """
     m = int(leaves_per_axis)
-    ncell = NX * m
-    tree = uniform_tree((m, m, m), (OUTFLOW,) * 3, (-0.5, -0.5, -0.5), 1.0 / ncell)
+    E = int(leaf_edge)
+    ncell = E * m
+    tree = uniform_tree((m, m, m), (OUTFLOW,) * 3, (-0.5, -0.5, -0.5), 1.0 / ncell, leaf_edge=E)
     n = tree.n
-    rho = np.full((n, NX, NX, NX), rho_amb)
+    rho = np.full((n, E, E, E), rho_amb)
     z = np.zeros_like(rho)
     p = np.full_like(rho, p_amb)
     U = conserved_from_primitive(rho, z, z, z, p, rho.copy(), gamma)
     dx = 1.0 / ncell
     c = ncell // 2
-    g = tree.coord[:, :, None] * NX + np.arange(NX)[None, None, :]      # [n, 3, 8] global index
+    g = tree.coord[:, :, None] * E + np.arange(E)[None, None, :]        # [n, 3, E] global index
     inx = (g[:, 0] == c - 1) | (g[:, 0] == c)
     iny = (g[:, 1] == c - 1) | (g[:, 1] == c)
     inz = (g[:, 2] == c - 1) | (g[:, 2] == c)

@@ -53,6 +53,7 @@ class Tree:
     level: np.ndarray
     coord: np.ndarray
     meta: dict = field(default_factory=dict)
+    leaf_edge: int = NX      # cells per leaf edge: 8, or 16 (eight 8^3 tiles per leaf)
 
     @property
     def n(self) -> int:
@@ -70,14 +71,16 @@ class Tree:
     def origin(self) -> np.ndarray:
         """Centre of cell (0,0,0) of every leaf, shape [n, 3]."""
         dx = self.dx[:, None]
-        return self.x0[None, :] + (NX * self.coord.astype(np.float64) + 0.5) * dx
+        return self.x0[None, :] + (self.leaf_edge * self.coord.astype(np.float64) + 0.5) * dx
 
     def cell_centres(self) -> np.ndarray:
-        """Centres of all interior cells, shape [n, 3, 8, 8, 8] as (x, y, z)[k][j][i]."""
+        """Centres of all interior cells, shape [n, 3, E, E, E] as (x, y, z)[k][j][i],
+        E = leaf_edge."""
         o = self.origin
         dx = self.dx
-        r = np.arange(NX, dtype=np.float64)
-        out = np.empty((self.n, 3, NX, NX, NX))
+        E = self.leaf_edge
+        r = np.arange(E, dtype=np.float64)
+        out = np.empty((self.n, 3, E, E, E))
         out[:, 0] = o[:, 0, None, None, None] + r[None, None, None, :] * dx[:, None, None, None]
         out[:, 1] = o[:, 1, None, None, None] + r[None, None, :, None] * dx[:, None, None, None]
         out[:, 2] = o[:, 2, None, None, None] + r[None, :, None, None] * dx[:, None, None, None]
@@ -92,10 +95,11 @@ class Tree:
             coord=np.ascontiguousarray(self.coord, dtype=np.int32),
             dx=np.ascontiguousarray(self.dx, dtype=np.float64),
             origin=np.ascontiguousarray(self.origin, dtype=np.float64),
+            leaf_edge=int(self.leaf_edge),
         )
 
 
-def _sorted_tree(nb, bc, x0, dx0, leaves: Iterable[tuple], meta=None) -> Tree:
+def _sorted_tree(nb, bc, x0, dx0, leaves: Iterable[tuple], meta=None, leaf_edge: int = NX) -> Tree:
     leaves = sorted(leaves)
     if not leaves:
         raise ValueError("empty tree")
@@ -108,25 +112,59 @@ def _sorted_tree(nb, bc, x0, dx0, leaves: Iterable[tuple], meta=None) -> Tree:
     order = np.lexsort((lv, key))
     return Tree(np.asarray(nb, np.int32), np.asarray(bc, np.int32),
                 np.asarray(x0, np.float64), float(dx0), lv[order], co[order],
-                dict(meta or {}))
+                dict(meta or {}), int(leaf_edge))
 
 
-def uniform_tree(nb=(1, 1, 1), bc=(PERIODIC,) * 3, x0=(0.0, 0.0, 0.0), dx0=1.0 / NX) -> Tree:
+def uniform_tree(nb=(1, 1, 1), bc=(PERIODIC,) * 3, x0=(0.0, 0.0, 0.0), dx0=1.0 / NX,
+                 leaf_edge: int = NX) -> Tree:
     """All leaves at level 0: a uniform grid of nb[0]*nb[1]*nb[2] leaves."""
     nb = tuple(int(v) for v in nb)
     leaves = [(0, i, j, k) for k in range(nb[2]) for j in range(nb[1]) for i in range(nb[0])]
-    return _sorted_tree(nb, bc, x0, dx0, leaves)
+    return _sorted_tree(nb, bc, x0, dx0, leaves, leaf_edge=leaf_edge)
+
+
+def split_octets(tree: Tree) -> Tree:
+    """The same mesh as leaves of 8^3 cells: leaf L of a 16^3-leaf tree becomes
+    the eight 8^3 leaves 8L + t, t = ti + 2 tj + 4 tk for the tile at cell
+    offset 8 (ti, tj, tk) (same levels, doubled root grid).  Cells, levels and
+    neighbour relations are unchanged, so every ghost cell has the same source."""
+    if tree.leaf_edge == NX:
+        return tree
+    assert tree.leaf_edge == 2 * NX
+    t = np.arange(8)
+    off = np.stack([t & 1, (t >> 1) & 1, t >> 2], axis=1)                # [8, 3]
+    coord = (2 * tree.coord[:, None, :] + off[None]).reshape(-1, 3)
+    level = np.repeat(tree.level, 8)
+    return Tree(2 * np.asarray(tree.nb, np.int32), np.asarray(tree.bc, np.int32),
+                np.asarray(tree.x0, np.float64), float(tree.dx0), level.astype(np.int32),
+                coord.astype(np.int32), dict(tree.meta), NX)
+
+
+def to_tiles8(U: np.ndarray) -> np.ndarray:
+    """[n, F, 16, 16, 16] -> [8 n, F, 8, 8, 8] in the leaf order of split_octets."""
+    n, F = U.shape[:2]
+    V = U.reshape(n, F, 2, NX, 2, NX, 2, NX)                 # (tk, k, tj, j, ti, i)
+    return np.ascontiguousarray(V.transpose(0, 2, 4, 6, 1, 3, 5, 7).reshape(8 * n, F, NX, NX, NX))
+
+
+def from_tiles8(V: np.ndarray) -> np.ndarray:
+    """Inverse of to_tiles8."""
+    m, F = V.shape[:2]
+    n = m // 8
+    W = V.reshape(n, 2, 2, 2, F, NX, NX, NX)                 # (tk, tj, ti, f, k, j, i)
+    return np.ascontiguousarray(W.transpose(0, 4, 1, 5, 2, 6, 3, 7).reshape(n, F, 2 * NX, 2 * NX, 2 * NX))
 
 
 class LeafSet:
     """Mutable leaf set used while refining; checks 2:1 balance on every split."""
 
-    def __init__(self, nb, bc, x0, dx0, leaves):
+    def __init__(self, nb, bc, x0, dx0, leaves, leaf_edge: int = NX):
         self.nb = np.asarray(nb, np.int64)
         self.bc = np.asarray(bc, np.int64)
         self.x0 = np.asarray(x0, np.float64)
         self.dx0 = float(dx0)
         self.leaves = set(leaves)
+        self.leaf_edge = int(leaf_edge)
 
     def slots(self, l: int) -> np.ndarray:
         return self.nb << l
@@ -170,7 +208,7 @@ class LeafSet:
                     self.leaves.add((l + 1, 2 * c[0] + ox, 2 * c[1] + oy, 2 * c[2] + oz))
 
     def node_box(self, l: int, c):
-        size = NX * self.dx0 / (1 << l)
+        size = self.leaf_edge * self.dx0 / (1 << l)
         lo = self.x0 + np.asarray(c, np.float64) * size
         return lo, lo + size
 
@@ -211,7 +249,7 @@ class LeafSet:
 
     def tree(self, meta=None) -> Tree:
         return _sorted_tree(tuple(self.nb), tuple(self.bc), tuple(self.x0), self.dx0,
-                            self.leaves, meta)
+                            self.leaves, meta, self.leaf_edge)
 
 
 def box_distance(lo, hi, p) -> float:

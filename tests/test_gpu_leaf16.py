@@ -1,0 +1,183 @@
+"""GPU parity of 16^3 leaves (eight 8^3 tiles each) against the CPU oracle.
+
+A mesh of 16^3 leaves is cell for cell the mesh of 8^3 leaves obtained by
+splitting every leaf into its eight octants (same levels, same neighbours,
+same ghost sources), so the oracle runs on that split tree and the results are
+compared tile by tile.  Tolerance (FP64): per field, max |gpu - oracle| /
+max |oracle_f| <= 1e-12."""
+import numpy as np
+import pytest
+
+from paper_2107_10987_amd.workloads import (OUTFLOW, PERIODIC, LeafSet, conserved_from_primitive,
+                                            from_tiles8, sedov_uniform, split_octets, to_tiles8)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+G = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def field_err(g, o):
+    g = np.asarray(g).reshape(g.shape[0], 7, -1)
+    o = np.asarray(o).reshape(o.shape[0], 7, -1)
+    return np.array([np.abs(g[:, f] - o[:, f]).max() / max(np.abs(o[:, f]).max(), 1e-300)
+                     for f in range(7)])
+
+
+def _amr16(bc=(PERIODIC,) * 3):
+    ls = LeafSet((2, 2, 2), bc, (0.0, 0.0, 0.0), 1.0 / 32,
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)], leaf_edge=16)
+    ls.refine(0, (0, 0, 0))
+    ls.refine(0, (1, 1, 1))
+    return ls.tree()
+
+
+def _state(tree, seed=5):
+    rng = np.random.default_rng(seed)
+    x = tree.cell_centres()
+    ph = rng.uniform(0, 2 * np.pi, size=6)
+    r2 = ((x[:, 0] - 0.45) ** 2 + (x[:, 1] - 0.5) ** 2 + (x[:, 2] - 0.55) ** 2)
+    rho = 1.0 + 2.0 * np.exp(-r2 / 0.02) + 0.2 * np.sin(2 * np.pi * x[:, 1] + ph[0])
+    vx = 0.5 + 0.3 * np.sin(2 * np.pi * (x[:, 1] + x[:, 2]) + ph[1])
+    vy = -0.4 + 0.2 * np.sin(2 * np.pi * (x[:, 0] + x[:, 2]) + ph[2])
+    vz = 0.3 * np.sin(2 * np.pi * (x[:, 0] + x[:, 1]) + ph[3])
+    p = 1.0 + 0.5 * np.exp(-r2 / 0.03) + 0.1 * np.sin(2 * np.pi * x[:, 0] + ph[4])
+    spc = rho * (0.5 + 0.4 * np.sin(2 * np.pi * x[:, 2] + ph[5]))
+    return np.ascontiguousarray(conserved_from_primitive(rho, vx, vy, vz, p, spc, G))
+
+
+def _leaf_max(a8):
+    return np.asarray(a8).reshape(-1, 8).max(axis=1)
+
+
+@pytest.mark.parametrize("schedule", ["column", "face", "persistent", "tiled"])
+def test_sedov_64_as_16cubed_leaves(torch, schedule):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: sedov-64^3 as 64 leaves of 16^3, 3 steps, schedule {schedule}", flush=True)
+    w = sedov_uniform(4, leaf_edge=16)
+    t8 = split_octets(w.tree)
+    o = oracle.Oracle(t8, w.gamma, w.omega)
+    U8 = to_tiles8(w.U)
+    hy = Hydro(max_leaves=w.n, schedule=schedule, leaf_edge=16)
+    try:
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        a = hy.signal_speed(g).cpu().numpy()
+        a8 = o.signal_speed(U8)
+        assert np.abs(a - _leaf_max(a8)).max() <= TOL * a8.max()
+        dt = float(w.cfl * np.min(w.tree.dx / a))
+        for s in range(3):
+            am = hy.step(g, dt)
+            U8, am8 = o.step(dt, U8)
+            err = field_err(to_tiles8(g.U.cpu().numpy()), U8)
+            print(f"step {s} err", err, flush=True)
+            assert np.all(err <= TOL), err
+            assert np.abs(am - _leaf_max(am8)).max() <= TOL * am8.max()
+            dt = float(w.cfl * np.min(w.tree.dx / am))
+    finally:
+        hy.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_amr_rotating_16cubed_leaves(torch, order):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: periodic AMR of 16^3 leaves (22 leaves), Omega 0.2, RK{order}", flush=True)
+    t16 = _amr16()
+    U16 = _state(t16)
+    t8 = split_octets(t16)
+    o = oracle.Oracle(t8, G, 0.2)
+    hy = Hydro(max_leaves=t16.n, leaf_edge=16, rk_order=order)
+    try:
+        g = hy.grid(t16, torch.tensor(U16, device="cuda"), 0.2, G)
+        U8 = to_tiles8(U16)
+        dt = o.dt(U8)
+        for s in range(2):
+            hy.step(g, dt)
+            U8, _ = o.step(dt, U8, order=order)
+            err = field_err(to_tiles8(g.U.cpu().numpy()), U8)
+            print(f"step {s} err", err, flush=True)
+            assert np.all(err <= TOL), err
+    finally:
+        hy.close()
+
+
+def test_uneven_launches_and_device_dt_16(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: 16^3 AMR, uneven launches (bitwise) and device-driven dt", flush=True)
+    t16 = _amr16((OUTFLOW, PERIODIC, OUTFLOW))
+    U16 = _state(t16, seed=8)
+    off = np.array([0, 1, 4, 5, 13, t16.n], np.int32)
+    one = Hydro(max_leaves=t16.n, leaf_edge=16, schedule="column")
+    many = Hydro(max_leaves=t16.n, leaf_edge=16, schedule="auto")
+    try:
+        ga = one.grid(t16, torch.tensor(U16, device="cuda"), 0.0, G)
+        gb = many.grid(t16, torch.tensor(U16, device="cuda"), 0.0, G, launch_off=off)
+        dt = float(0.4 * np.min(t16.dx / one.signal_speed(ga).cpu().numpy()))
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        many.dt(gb, 0.4, dt_dev)
+        assert dt_dev.item() == dt
+        for _ in range(3):
+            am = one.step(ga, dt)
+            dt = float(0.4 * np.min(t16.dx / am))
+            many.step_dev(gb, 0.4, dt_dev)
+            assert dt_dev.item() == dt
+        assert torch.equal(ga.U, gb.U)
+    finally:
+        one.close()
+        many.close()
+
+
+def test_learned_nan_network_16_is_the_plain_step(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: 16^3 leaves, learned path with a NaN network == plain step", flush=True)
+    w = sedov_uniform(2, leaf_edge=16)
+    U = w.U.copy()
+    p = (np.random.default_rng(7).normal(size=8090) * 0.3).astype(np.float32)
+    p[8064:] = np.nan
+    plain = Hydro(max_leaves=w.n, leaf_edge=16, schedule="column")
+    lrn = Hydro(max_leaves=w.n, leaf_edge=16, schedule="column", learned=True)
+    try:
+        lrn.mlp_load(p)
+        ga = plain.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        gb = lrn.grid(w.tree, torch.tensor(U, device="cuda"), w.omega, w.gamma)
+        dt = float(w.cfl * np.min(w.tree.dx / plain.signal_speed(ga).cpu().numpy()))
+        aa = plain.step(ga, dt)
+        ab = lrn.step(gb, dt)
+        cells, fb = lrn.mlp_stats()
+        assert cells == 3 * w.n * 8 * 896       # the signal-speed pre-pass and both stages
+        assert torch.equal(ga.U, gb.U) and np.array_equal(aa, ab)
+    finally:
+        plain.close()
+        lrn.close()
+
+
+def test_leaf16_errors(torch):
+    from paper_2107_10987_amd.hydro import EINVAL, Hydro, HydroError
+    with pytest.raises(HydroError) as e:
+        Hydro(max_leaves=8, leaf_edge=16, reflux=True)
+    assert e.value.code == EINVAL
+    with pytest.raises(HydroError) as e:
+        Hydro(max_leaves=8, leaf_edge=12)
+    assert e.value.code == EINVAL
+    w = sedov_uniform(2, leaf_edge=16)
+    hy = Hydro(max_leaves=w.n, leaf_edge=16)
+    h8 = Hydro(max_leaves=w.n * 8)
+    try:
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        with pytest.raises(HydroError) as e:
+            hy.reconstruct(g)
+        assert e.value.code == EINVAL
+        with pytest.raises(ValueError):
+            h8.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+    finally:
+        hy.close()
+        h8.close()
+

@@ -187,3 +187,65 @@ def test_reflux_map_rejects_unbalanced_tree():
     with pytest.raises(hydro.HydroError) as e:
         hydro.reflux_map(ls.tree())
     assert e.value.code == hydro.EINVAL
+
+
+def _apply_map16(U16, gm16):
+    """Padded 14^3 blocks of every 8^3 tile of 16^3 leaves from the library's
+    ghost map, on the host ([8 n, 7, 14, 14, 14] in split_octets order)."""
+    n = U16.shape[0]
+    flat = U16.reshape(n, 7, 4096)
+    r = np.arange(-3, 11)
+    K, J, I = np.meshgrid(r, r, r, indexing="ij")
+    ghost = ~((I >= 0) & (I < 8) & (J >= 0) & (J < 8) & (K >= 0) & (K < 8))
+    gidx = np.nonzero(ghost.ravel())[0]
+    P = np.zeros((8 * n, 7, 14 ** 3))
+    for l in range(n):
+        for t in range(8):
+            ti, tj, tk = t & 1, (t >> 1) & 1, t >> 2
+            blk = U16[l, :, 8 * tk:8 * tk + 8, 8 * tj:8 * tj + 8, 8 * ti:8 * ti + 8].reshape(7, 512)
+            Pb = P[8 * l + t]
+            Pb[:, ~ghost.ravel()] = blk
+            s = gm16[l, t]
+            cp = s >= 0
+            src = s[cp]
+            Pb[:, gidx[cp]] = flat[src // 4096, :, src % 4096].T
+            b = -s[~cp] - 1
+            if b.size:
+                acc = np.zeros((7, b.size))
+                for off in (0, 1, 16, 17, 256, 257, 272, 273):
+                    acc = acc + flat[b // 4096, :, b % 4096 + off].T
+                Pb[:, gidx[~cp]] = acc * 0.125
+    return P.reshape(8 * n, 7, 14, 14, 14)
+
+
+@needs_lib
+@pytest.mark.parametrize("bc,refine", [((PERIODIC,) * 3, False), ((PERIODIC,) * 3, True),
+                                       ((OUTFLOW, PERIODIC, OUTFLOW), True)])
+def test_ghost_map_16_matches_oracle_on_split_tree(oracle_mod, bc, refine):
+    from paper_2107_10987_amd.workloads import split_octets, to_tiles8
+    ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / 32,
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)], leaf_edge=16)
+    if refine:
+        ls.refine(0, (0, 0, 0))
+    tree = ls.tree()
+    assert tree.leaf_edge == 16
+    rng = np.random.default_rng(3)
+    U16 = rng.uniform(0.5, 2.0, size=(tree.n, 7, 16, 16, 16))
+    gm = hydro.ghost_map(tree)
+    assert gm.shape == (tree.n, 8, 2232)
+    t8 = split_octets(tree)
+    o = oracle_mod.Oracle(t8, 5 / 3, 0.0)
+    P8 = o.padded(to_tiles8(U16))
+    P = _apply_map16(U16, gm)
+    assert np.array_equal(P, P8)
+
+
+def test_split_octets_round_trip():
+    from paper_2107_10987_amd.workloads import from_tiles8, sedov_uniform, split_octets, to_tiles8
+    a, b = sedov_uniform(4), sedov_uniform(2, leaf_edge=16)
+    t8, U8 = split_octets(b.tree), to_tiles8(b.U)
+    assert np.array_equal(from_tiles8(U8), b.U)
+    key = {tuple(c): i for i, c in enumerate(a.tree.coord)}
+    perm = [key[tuple(c)] for c in t8.coord]
+    assert np.array_equal(U8, a.U[perm])
+    assert np.array_equal(t8.origin, a.tree.origin[perm]) and np.array_equal(t8.dx, a.tree.dx[perm])
