@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2107_10987_amd.workloads import (OUTFLOW, PERIODIC, LeafSet, conserved_from_primitive,
-                                            from_tiles8, sedov_uniform, split_octets, to_tiles8)
+                                            sedov_uniform, split_octets, to_tiles8)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
