@@ -241,6 +241,45 @@ def batched_legs(torch, args, params):
     return out
 
 
+def leaf16_leg(torch, args):
+    """The same 64^3 Sedov workload held as 64 leaves of 16^3 cells (the
+    paper's production leaf size; each leaf is eight 8^3 tiles, one workgroup
+    each): --steps device-dt steps, stage-kernel time from HIP events."""
+    from paper_2107_10987_amd.hydro import Hydro
+    from paper_2107_10987_amd.workloads import sedov_uniform
+
+    w = sedov_uniform(4, leaf_edge=16)
+    hy = Hydro(max_leaves=w.n, schedule=args.schedule, leaf_edge=16)
+    try:
+        U0 = torch.tensor(w.U, device="cuda")
+        g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def run(nsteps, timed=False):
+            g.U.copy_(U0)
+            if timed:
+                hy.timing(True)
+            hy.dt(g, w.cfl, dt_dev)
+            for _ in range(nsteps):
+                hy.step_dev(g, w.cfl, dt_dev)
+
+        run(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(args.steps, timed=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kms, launches = hy.timing(False)
+        hy.check()
+        avg = kms / 1e3 / max(launches, 1)
+        return {"workload": "sedov-64^3 as 64 leaves of 16^3 cells (512 tiles of 8^3)",
+                "value": w.cells * 2 * args.steps / el, "unit": "cell-updates/s",
+                "ms_per_step": el / args.steps * 1e3, "avg_launch_us": avg * 1e6,
+                "kernel_cell_updates_per_s": w.cells / avg}
+    finally:
+        hy.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +355,7 @@ def main():
                 "frac": achieved_gbs / PEAK_HBM_GBS},
     }
     hy.close()
+    out["leaf16"] = leaf16_leg(torch, args)
     if not args.no_batched:
         params, info = train_network(torch, args)
         out["batched"] = batched_legs(torch, args, params)
