@@ -57,6 +57,7 @@ def lib():
         L.oracle_tree_create.argtypes = [ip, ip, C.c_int, ip, ip]
         L.oracle_tree_create.restype = C.c_void_p
         L.oracle_tree_destroy.argtypes = [C.c_void_p]
+        L.oracle_tree_set_prolong.argtypes = [C.c_void_p, C.c_int]
         L.oracle_fill_padded.argtypes = [C.c_void_p, dp, C.c_int, C.c_int, dp]
         L.oracle_leaf_reconstruct.argtypes = [dp, dp]
         L.oracle_leaf_fluxes.argtypes = [dp, C.c_double, dp, C.POINTER(Phys), dp]
@@ -122,7 +123,7 @@ class Oracle:
     """
 
     def __init__(self, tree, gamma=5 / 3, omega=0.0, eta1=1e-3, eta2=1e-1, threads=None,
-                 centre_only=False, reflux=False):
+                 centre_only=False, reflux=False, prolong=False):
         a = tree.arrays()
         self._keep = a
         self.n = tree.n
@@ -135,6 +136,7 @@ class Oracle:
                                            _p(a["level"], C.c_int), _p(a["coord"], C.c_int))
         if not self._t:
             raise RuntimeError("oracle_tree_create failed")
+        lib().oracle_tree_set_prolong(self._t, int(bool(prolong)))
         del ip
 
     def __del__(self):

@@ -162,6 +162,7 @@ double oracle_point_flux(int n, const double UL[7], const double UR[7], const do
 
 typedef struct {
     int nb[3], bc[3], n, lmax;
+    int prolong; /* 1: linear-limited prolongation of ghosts from coarser leaves */
     const int *level, *coord;
     long dim[MAXLEV][3];
     int *slot[MAXLEV]; /* leaf index of each level-l slot, -1 if none */
@@ -238,6 +239,72 @@ static int cell_value(const tree_t *t, const double *U, int l, const long g[3], 
     return 0;
 }
 
+void oracle_tree_set_prolong(void *tp, int on)
+{
+    ((tree_t *)tp)->prolong = on;
+}
+
+/* Level of the leaf covering level-l cell g when that leaf is at level <= l,
+ * else -1 (the cell is refined). */
+static int covering_level(const tree_t *t, int l, const long g[3])
+{
+    for (int lc = (l < t->lmax ? l : t->lmax); lc >= 0; --lc) {
+        long s[3];
+        for (int a = 0; a < 3; ++a) s[a] = (g[a] >> (l - lc)) / NX;
+        if (t->slot[lc][(s[2] * t->dim[lc][1] + s[1]) * t->dim[lc][0] + s[0]] >= 0) return lc;
+    }
+    return -1;
+}
+
+static double minmod(double a, double b)
+{
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+/* Ghost value of level-l cell g.  Without prolongation (and wherever the cell
+ * is not covered by a coarser leaf) it is cell_value's.  With it, a cell inside
+ * the cell C of a coarser leaf takes the linear reconstruction of C at its
+ * centre: U_C + sum over axes of (offset of the centre from C's, in units of
+ * C's size) x minmod(U_{C+e} - U_C, U_C - U_{C-e}), the neighbours taken at C's
+ * level by the same rules (wrap or clamp, injection, mean of finer cells), and
+ * the three terms added in x, y, z order.  The paper's AMR (section IV-B)
+ * leaves the coarse-to-fine ghost interpolation unspecified; this is the
+ * usual conservative, monotonicity-preserving choice. */
+static int ghost_value(const tree_t *t, const double *U, int l, const long g[3], double out[7])
+{
+    if (!t->prolong) return cell_value(t, U, l, g, out);
+    const int lc = covering_level(t, l, g);
+    if (lc < 0 || lc == l) return cell_value(t, U, l, g, out);
+    const int d = l - lc;
+    long C[3];
+    double frac[3];
+    for (int a = 0; a < 3; ++a) {
+        C[a] = g[a] >> d;
+        frac[a] = ((double)(g[a] - (C[a] << d)) + 0.5) / (double)(1L << d) - 0.5;
+    }
+    double uc[7];
+    if (cell_value(t, U, lc, C, uc)) return -1;
+    for (int f = 0; f < NFLD; ++f) out[f] = uc[f];
+    for (int a = 0; a < 3; ++a) {
+        double um[7], up[7];
+        long cm[3] = {C[0], C[1], C[2]}, cp[3] = {C[0], C[1], C[2]};
+        const long ncell = (long)NX * t->dim[lc][a];
+        cm[a] = C[a] - 1;
+        cp[a] = C[a] + 1;
+        if (t->bc[a] == 0) {
+            cm[a] = (cm[a] + ncell) % ncell;
+            cp[a] = cp[a] % ncell;
+        } else {
+            if (cm[a] < 0) cm[a] = 0;
+            if (cp[a] >= ncell) cp[a] = ncell - 1;
+        }
+        if (cell_value(t, U, lc, cm, um) || cell_value(t, U, lc, cp, up)) return -1;
+        for (int f = 0; f < NFLD; ++f) out[f] = out[f] + frac[a] * minmod(up[f] - uc[f], uc[f] - um[f]);
+    }
+    return 0;
+}
+
 int oracle_fill_padded(const void *tp, const double *U, int l0, int l1, double *P)
 {
     const tree_t *t = (const tree_t *)tp;
@@ -267,7 +334,7 @@ int oracle_fill_padded(const void *tp, const double *U, int l0, int l1, double *
                                     g[a] = g[a] < 0 ? 0 : ncell - 1;
                             }
                         }
-                        if (cell_value(t, U, l, g, v)) return -1;
+                        if (ghost_value(t, U, l, g, v)) return -1;
                     }
                     for (int f = 0; f < NFLD; ++f) B[(long)f * NPAD + pidx(i, j, k)] = v[f];
                 }

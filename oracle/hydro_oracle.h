@@ -48,6 +48,9 @@ double oracle_point_flux(int n, const double UL[7], const double UR[7], const do
 void *oracle_tree_create(const int nb[3], const int bc[3], int n, const int *level,
                          const int *coord);
 void oracle_tree_destroy(void *t);
+/* on = 1: ghost cells inside a coarser leaf's cell take its minmod-limited
+ * linear reconstruction instead of its value (see oracle_fill_padded). */
+void oracle_tree_set_prolong(void *t, int on);
 
 /* Ghost-padded blocks of leaves [l0, l1) built from U. Returns 0, or -1 when a
  * ghost cell has no covering leaf. */

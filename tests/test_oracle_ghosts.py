@@ -69,3 +69,93 @@ def test_ghosts_match_geometric_search(oracle_mod, bc):
             got = P[leaf, :, k + 3, j + 3, i + 3]
             assert np.allclose(got, exp, rtol=1e-14, atol=1e-14), (leaf, i, j, k)
         assert np.array_equal(P[leaf, :, 3:11, 3:11, 3:11], U[leaf])
+
+
+# --- linear-limited prolongation of ghosts from coarser leaves ---------------
+
+def _interior_refined_tree():
+    """4^3 root leaves with outflow faces, the leaf (1,1,1) split: its ghost
+    cells lie in level-0 cells whose neighbours are level-0 cells or the split
+    leaf, never clamped at the box."""
+    ls = LeafSet((4, 4, 4), (OUTFLOW,) * 3, (0.0, 0.0, 0.0), 1.0 / 32,
+                 [(0, i, j, k) for i in range(4) for j in range(4) for k in range(4)])
+    ls.refine(0, (1, 1, 1))
+    return ls.tree()
+
+
+def _fine_ghosts_in_coarse(tree):
+    """(leaf, i, j, k) of ghost cells of level-1 leaves that lie in a level-0 leaf."""
+    out = []
+    size = NX * tree.dx
+    lo = tree.x0[None, :] + tree.coord * size[:, None]
+    for leaf in np.nonzero(tree.level == 1)[0]:
+        for k in range(-3, 11):
+            for j in range(-3, 11):
+                for i in range(-3, 11):
+                    if 0 <= i < 8 and 0 <= j < 8 and 0 <= k < 8:
+                        continue
+                    x = lo[leaf] + (np.array([i, j, k]) + 0.5) * tree.dx[leaf]
+                    inside = np.all((x[None, :] >= lo) & (x[None, :] < lo + size[:, None]), axis=1)
+                    o = np.nonzero(inside)[0][0]
+                    if tree.level[o] == 0:
+                        out.append((int(leaf), i, j, k, x))
+    return out
+
+
+def test_prolongation_is_exact_for_linear_fields(oracle_mod):
+    tree = _interior_refined_tree()
+    xc = tree.cell_centres()
+    U = np.stack([lin(xc[n].reshape(3, -1)).reshape(7, 8, 8, 8) for n in range(tree.n)])
+    o = oracle_mod.Oracle(tree, 5 / 3, 0.0, prolong=True)
+    P = o.padded(U)
+    cases = _fine_ghosts_in_coarse(tree)
+    assert len(cases) > 1000
+    for (leaf, i, j, k, x) in cases:
+        got = P[leaf, :, k + 3, j + 3, i + 3]
+        assert np.allclose(got, lin(x[:, None])[:, 0], rtol=1e-14, atol=1e-14), (leaf, i, j, k)
+    # without prolongation the same cells hold the coarse cell's value instead
+    P0 = oracle_mod.Oracle(tree, 5 / 3, 0.0).padded(U)
+    leaf, i, j, k, x = cases[0]
+    assert not np.allclose(P0[leaf, :, k + 3, j + 3, i + 3], lin(x[:, None])[:, 0], rtol=1e-6)
+
+
+def test_prolongation_conserves_each_coarse_cell(oracle_mod):
+    tree = _interior_refined_tree()
+    rng = np.random.default_rng(4)
+    U = rng.uniform(0.5, 2.0, size=(tree.n, 7, 8, 8, 8))
+    P = oracle_mod.Oracle(tree, 5 / 3, 0.0, prolong=True).padded(U)
+    P0 = oracle_mod.Oracle(tree, 5 / 3, 0.0).padded(U)   # injection: the coarse values
+    groups = {}
+    for (leaf, i, j, k, x) in _fine_ghosts_in_coarse(tree):
+        groups.setdefault((leaf,) + tuple(np.floor(x * 32).astype(int)), []).append((i, j, k))
+    full = [(key, cells) for key, cells in groups.items() if len(cells) == 8]
+    assert len(full) > 100
+    differs = 0
+    for (key, cells) in full:
+        leaf = key[0]
+        vals = np.array([P[leaf, :, k + 3, j + 3, i + 3] for (i, j, k) in cells])
+        coarse = np.array([P0[leaf, :, k + 3, j + 3, i + 3] for (i, j, k) in cells])
+        assert np.all(coarse == coarse[:1])                 # one coarse cell
+        assert np.allclose(vals.mean(axis=0), coarse[0], rtol=1e-15, atol=0.0), key
+        differs += not np.all(vals == coarse)
+    # at a cell that is an extremum along every axis in every field the
+    # slopes vanish; elsewhere the children differ from plain injection
+    assert differs > 0.9 * len(full)
+
+
+def test_prolongation_is_flat_at_an_extremum(oracle_mod):
+    tree = _interior_refined_tree()
+    xc = tree.cell_centres()
+    # a peak at the centre of the level-0 cell (7, 8, 8) (level-0 cell units),
+    # next to the split leaf, whose cells 16, 17 (level 1) see it as ghosts
+    peak = np.array([7.5, 8.5, 8.5]) / 32
+    r2 = ((xc - peak[None, :, None, None, None]) ** 2).sum(axis=1)
+    U = np.repeat((1.0 + np.exp(-r2 / 0.01))[:, None], 7, axis=1)
+    o = oracle_mod.Oracle(tree, 5 / 3, 0.0, prolong=True)
+    P, P0 = o.padded(U), oracle_mod.Oracle(tree, 5 / 3, 0.0).padded(U)
+    hits = 0
+    for (leaf, i, j, k, x) in _fine_ghosts_in_coarse(tree):
+        if np.all(np.floor(x * 32) == [7, 8, 8]):
+            assert np.array_equal(P[leaf, :, k + 3, j + 3, i + 3], P0[leaf, :, k + 3, j + 3, i + 3])
+            hits += 1
+    assert hits == 8
