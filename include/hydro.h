@@ -98,6 +98,8 @@ typedef struct hydro_grid {
     const int32_t *face_flags; /* device [n] from hydro_reflux_map, or NULL without  */
     const int32_t *reflux;     /*   reflux; device [n_reflux][26] correction list    */
     int32_t n_reflux;          /*   entries in the list (may be 0)                   */
+    const int32_t *prolong;    /* device [n_prolong][8] from hydro_ghost_map_linear  */
+    int32_t n_prolong;         /*   (NULL, 0 with a plain ghost map)                 */
 } hydro_grid;
 
 /* Octree description used to build the ghost map (host memory). */
@@ -126,6 +128,21 @@ int hydro_destroy(hydro_t *h);
  * Returns HYDRO_EINVAL if the tree is not 2:1 balanced or a leaf is outside
  * the box.  Synchronous; needs no handle and no GPU. */
 int hydro_ghost_map(const hydro_tree *t, int32_t *map);
+
+/* hydro_ghost_map with linear-limited prolongation: a ghost cell inside a
+ * coarser leaf's cell C gets, instead of C's value, U_C plus for each axis
+ * (+-1/4) minmod(U_{C+e} - U_C, U_C - U_{C-e}) (the sign by the half of C the
+ * ghost cell lies in; the neighbours at C's level by the same rules as ghost
+ * cells; the terms added in x, y, z order).  The paper's AMR (section IV-B)
+ * leaves coarse-to-fine ghost values unspecified; this is the conservative,
+ * monotonicity-preserving linear choice.  Such ghost cells get map entries
+ * s < -2^30 naming row -s-2^30-1 of table[capacity][8]: {C, C-x, C+x, C-y,
+ * C+y, C-z, C+z (each a copy or mean entry as in the ghost map), side bits
+ * (bit a: upper half along axis a)}.  *n_table receives the rows needed;
+ * HYDRO_ENOMEM if that exceeds capacity.  Needs n * E^3 < 2^30.  Synchronous;
+ * needs no handle and no GPU.  Pass the table as hydro_grid.prolong. */
+int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, int32_t capacity,
+                           int32_t *n_table);
 
 /* Coarse/fine face lists of a tree for the flux correction (host memory,
  * caller-owned).  The paper runs the scheme on an AMR octree (section IV-B)

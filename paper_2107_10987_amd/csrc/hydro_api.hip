@@ -134,6 +134,8 @@ int check_grid(hydro_t *h, const hydro_grid *g) {
     } else if (g->face_flags || g->n_reflux) {
         return fail(h, HYDRO_EINVAL, "grid carries reflux lists but the handle was created without reflux");
     }
+    if (g->n_prolong < 0 || (g->n_prolong > 0 && !g->prolong))
+        return fail(h, HYDRO_EINVAL, "bad prolongation table");
     if (g->n_launch < 0) return fail(h, HYDRO_EINVAL, "n_launch < 0");
     if (g->n_launch > 0) {
         if (!g->launch_off) return fail(h, HYDRO_EINVAL, "launch_off is NULL");
@@ -255,6 +257,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.centre_only = h->p.scheme == 1;
     a.ts = h->ts;
     a.lg = h->lg;
+    a.prolong = g->prolong;
+    a.n_prolong = g->n_prolong;
     const bool reflux = h->p.reflux && stage != 0;
     a.face_flags = reflux ? g->face_flags : nullptr;
     a.bflux = reflux ? h->bflux : nullptr;
@@ -283,6 +287,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.leaf0 = a.leaf0;
             m.ts = h->ts;
             m.lg = h->lg;
+            m.prolong = g->prolong;
+            m.n_prolong = g->n_prolong;
             hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, s);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
             h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
@@ -449,6 +455,117 @@ int check_batch(hydro_t *h, const void *X, int B) {
     return HYDRO_OK;
 }
 
+
+// Ghost maps of every tile of every leaf; with `table` non-NULL, ghost cells
+// inside a coarser leaf get a linear-prolongation row instead of a copy.
+int build_ghost_map(const hydro_tree *t, int32_t *map, int32_t *table, int32_t capacity,
+                    int32_t *n_table) {
+    if (!map) return fail(nullptr, HYDRO_EINVAL, "null map");
+    TreeIndex ti;
+    int rc = ti.build(t);
+    if (rc) return rc;
+    const int lmax = ti.lmax;
+    const int lg = t->leaf_edge == 16 ? 4 : 3;   // build() accepted 0, 8 or 16
+    const int64_t E = (int64_t)1 << lg;
+    const int tiles = t->leaf_edge == 16 ? 8 : 1;
+    const bool linear = n_table != nullptr;
+    if (linear && (int64_t)t->n * E * E * E >= PROLONG_BASE)
+        return fail(nullptr, HYDRO_EINVAL, "too many leaves for a prolongation map");
+    // the leaf at level l holding global cell g (cells of that level), and
+    // the cell's index inside that leaf
+    auto find = [&](int l, const int64_t g[3]) -> int32_t { return ti.leaf(l, g[0] >> lg, g[1] >> lg, g[2] >> lg); };
+    auto local = [&](const int64_t g[3]) -> int32_t {
+        return (int32_t)((((g[2] & (E - 1)) * E + (g[1] & (E - 1))) * E) + (g[0] & (E - 1)));
+    };
+    const int32_t cells = (int32_t)(E * E * E);
+    // wrap or clamp global cell g of level l into the box, in place
+    auto fold = [&](int l, int64_t g[3]) {
+        for (int a = 0; a < 3; ++a) {
+            const int64_t nc = E * t->nb[a] << l;
+            if (g[a] < 0 || g[a] >= nc) {
+                if (t->bc[a] == 0) g[a] = ((g[a] % nc) + nc) % nc;
+                else g[a] = g[a] < 0 ? 0 : nc - 1;
+            }
+        }
+    };
+    // map entry of level-l cell g: a copy from the leaf covering it at level
+    // <= l (injection), else the mean of its 2x2x2 cells one level finer;
+    // *covering = level of the covering leaf, or l + 1
+    std::string err;
+    auto entry = [&](int l, const int64_t g[3], int *covering) -> int64_t {
+        for (int lc = l; lc >= 0; --lc) {
+            const int64_t gc[3] = {g[0] >> (l - lc), g[1] >> (l - lc), g[2] >> (l - lc)};
+            const int32_t o = find(lc, gc);
+            if (o >= 0) {
+                *covering = lc;
+                return (int64_t)o * cells + local(gc);
+            }
+        }
+        const int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
+        const int32_t o = (l < lmax) ? find(l + 1, gf) : -1;
+        if (o < 0) return INT64_MIN;
+        *covering = l + 1;
+        return -((int64_t)o * cells + local(gf)) - 1;
+    };
+    int32_t rows = 0;
+    for (int i = 0; i < t->n; ++i) {
+        const int l = t->level[i];
+        const int32_t *c = t->coord + 3 * (size_t)i;
+        for (int tile = 0; tile < tiles; ++tile) {
+            const int to[3] = {8 * (tile & 1), 8 * ((tile >> 1) & 1), 8 * (tile >> 2)};
+            int32_t *m = map + ((size_t)i * tiles + tile) * NG;
+            int s = 0;
+            for (int k = -GW; k < NX + GW; ++k)
+                for (int j = -GW; j < NX + GW; ++j)
+                    for (int ii = -GW; ii < NX + GW; ++ii) {
+                        if (ii >= 0 && ii < NX && j >= 0 && j < NX && k >= 0 && k < NX) continue;
+                        const int off[3] = {ii, j, k};
+                        int64_t g[3];
+                        for (int a = 0; a < 3; ++a) g[a] = E * c[a] + to[a] + off[a];
+                        fold(l, g);
+                        int lc = 0;
+                        const int64_t src = entry(l, g, &lc);
+                        if (src == INT64_MIN)
+                            return fail(nullptr, HYDRO_EINVAL,
+                                        "ghost cell of leaf " + std::to_string(i) +
+                                            " is neither covered nor refined once (tree not 2:1 balanced)");
+                        if (!linear || lc >= l) {
+                            m[s++] = (int32_t)src;
+                            continue;
+                        }
+                        if (lc != l - 1)
+                            return fail(nullptr, HYDRO_EINVAL, "ghost cell two levels coarser (tree not 2:1 balanced)");
+                        // prolongation row: the coarse cell C, its six neighbours
+                        // at C's level, and the side of g within C per axis
+                        if (rows < capacity && table) {
+                            int32_t *r = table + (size_t)rows * PROLONG_ROW;
+                            const int64_t C[3] = {g[0] >> 1, g[1] >> 1, g[2] >> 1};
+                            int lcc = 0;
+                            r[0] = (int32_t)entry(lc, C, &lcc);
+                            for (int a = 0; a < 3; ++a)
+                                for (int side = 0; side < 2; ++side) {
+                                    int64_t q[3] = {C[0], C[1], C[2]};
+                                    q[a] += side ? 1 : -1;
+                                    fold(lc, q);
+                                    const int64_t e = entry(lc, q, &lcc);
+                                    if (e == INT64_MIN)
+                                        return fail(nullptr, HYDRO_EINVAL, "coarse neighbour not covered (tree not 2:1 balanced)");
+                                    r[1 + 2 * a + side] = (int32_t)e;
+                                }
+                            r[7] = (int32_t)((g[0] & 1) | ((g[1] & 1) << 1) | ((g[2] & 1) << 2));
+                        }
+                        m[s++] = -PROLONG_BASE - 1 - rows;
+                        ++rows;
+                    }
+        }
+    }
+    if (linear) {
+        *n_table = rows;
+        if (rows > capacity) return fail(nullptr, HYDRO_ENOMEM, "prolongation table needs " + std::to_string(rows) + " rows");
+    }
+    return HYDRO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -599,7 +716,8 @@ int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out) {
     if (!g->U || !out) return fail(h, HYDRO_EINVAL, "null U or out");
     if (h->ts) return fail(h, HYDRO_EINVAL, "hydro_reconstruct supports 8^3 leaves only");
     if ((rc = set_device(h))) return rc;
-    hipError_t e = hydro_launch_reconstruct(g->U, g->ghost_map, g->n, out, (hipStream_t)g->stream);
+    hipError_t e = hydro_launch_reconstruct(g->U, g->ghost_map, g->prolong, g->n_prolong, g->n, out,
+                                            (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "reconstruct launch");
 }
 
@@ -792,7 +910,8 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
     if (!g->U || !X || !T || !valid) return fail(h, HYDRO_EINVAL, "null U or pair buffer");
     if (h->ts) return fail(h, HYDRO_EINVAL, "hydro_mlp_pairs supports 8^3 leaves only");
     if ((rc = set_device(h))) return rc;
-    hipError_t e = hydro_launch_pairs(g->U, g->ghost_map, g->n, X, T, valid, (hipStream_t)g->stream);
+    hipError_t e = hydro_launch_pairs(g->U, g->ghost_map, g->prolong, g->n_prolong, g->n, X, T, valid,
+                                      (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "pairs launch");
 }
 
@@ -865,71 +984,16 @@ const char *hydro_last_error(const hydro_t *h) { return h ? h->err.c_str() : g_c
 // Ghost map of an octree (host)
 // ---------------------------------------------------------------------------
 
+
 int hydro_ghost_map(const hydro_tree *t, int32_t *map) {
-    if (!map) return fail(nullptr, HYDRO_EINVAL, "null map");
-    TreeIndex ti;
-    int rc = ti.build(t);
-    if (rc) return rc;
-    const int lmax = ti.lmax;
-    const int lg = t->leaf_edge == 16 ? 4 : 3;   // build() accepted 0, 8 or 16
-    const int64_t E = (int64_t)1 << lg;
-    const int tiles = t->leaf_edge == 16 ? 8 : 1;
-    // the leaf at level l holding global cell g (cells of that level), and
-    // the cell's index inside that leaf
-    auto find = [&](int l, const int64_t g[3]) -> int32_t { return ti.leaf(l, g[0] >> lg, g[1] >> lg, g[2] >> lg); };
-    auto local = [&](const int64_t g[3]) -> int32_t {
-        return (int32_t)((((g[2] & (E - 1)) * E + (g[1] & (E - 1))) * E) + (g[0] & (E - 1)));
-    };
-    const int32_t cells = (int32_t)(E * E * E);
-    for (int i = 0; i < t->n; ++i) {
-        const int l = t->level[i];
-        const int32_t *c = t->coord + 3 * (size_t)i;
-        for (int tile = 0; tile < tiles; ++tile) {
-            const int to[3] = {8 * (tile & 1), 8 * ((tile >> 1) & 1), 8 * (tile >> 2)};
-            int32_t *m = map + ((size_t)i * tiles + tile) * NG;
-            int s = 0;
-            for (int k = -GW; k < NX + GW; ++k)
-                for (int j = -GW; j < NX + GW; ++j)
-                    for (int ii = -GW; ii < NX + GW; ++ii) {
-                        if (ii >= 0 && ii < NX && j >= 0 && j < NX && k >= 0 && k < NX) continue;
-                        const int off[3] = {ii, j, k};
-                        int64_t g[3];
-                        for (int a = 0; a < 3; ++a) {
-                            const int64_t nc = E * t->nb[a] << l;
-                            int64_t v = E * c[a] + to[a] + off[a];
-                            if (v < 0 || v >= nc) {
-                                if (t->bc[a] == 0) v = ((v % nc) + nc) % nc;
-                                else v = v < 0 ? 0 : nc - 1;
-                            }
-                            g[a] = v;
-                        }
-                        int32_t src = -1;
-                        bool found = false;
-                        // a leaf at this level or coarser covering the cell (the
-                        // leaf itself for cells of its other tiles)
-                        for (int lc = l; lc >= 0 && !found; --lc) {
-                            const int64_t gc[3] = {g[0] >> (l - lc), g[1] >> (l - lc), g[2] >> (l - lc)};
-                            const int32_t o = find(lc, gc);
-                            if (o >= 0) {
-                                src = o * cells + local(gc);
-                                found = true;
-                            }
-                        }
-                        if (!found) {
-                            // refined: its 2x2x2 children must belong to one leaf of level l+1
-                            const int64_t gf[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
-                            const int32_t o = (l < lmax) ? find(l + 1, gf) : -1;
-                            if (o < 0)
-                                return fail(nullptr, HYDRO_EINVAL,
-                                            "ghost cell of leaf " + std::to_string(i) +
-                                                " is neither covered nor refined once (tree not 2:1 balanced)");
-                            src = -(o * cells + local(gf)) - 1;
-                        }
-                        m[s++] = src;
-                    }
-        }
-    }
-    return HYDRO_OK;
+    return build_ghost_map(t, map, nullptr, 0, nullptr);
+}
+
+int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, int32_t capacity,
+                           int32_t *n_table) {
+    if (!n_table) return fail(nullptr, HYDRO_EINVAL, "null n_table");
+    if (capacity < 0) return fail(nullptr, HYDRO_EINVAL, "capacity < 0");
+    return build_ghost_map(t, map, table, capacity, n_table);
 }
 
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries) {

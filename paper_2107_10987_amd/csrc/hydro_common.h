@@ -69,6 +69,9 @@ struct StageArgs {
     double *bflux;              // [n][6][7][64] Simpson flux of flagged boundary faces
     // leaf edge E = 1 << lg cells (8 or 16); kernels work on 8^3 blocks, 1 << ts per leaf
     int ts, lg;
+    // linear-prolongation rows named by ghost-map entries below -PROLONG_BASE
+    const int32_t *prolong;   // [n_prolong][PROLONG_ROW] or null
+    int n_prolong;
 };
 
 // Leaves of E = 2^lg cells per edge (8 or 16) are processed as (E/8)^3 tiles
@@ -91,6 +94,63 @@ __device__ __forceinline__ int block_cell(int c, int lg) {
 __device__ __forceinline__ size_t src_offset(int s, int lg) {
     const int sh = 3 * lg;
     return ((size_t)(s >> sh) * NF << sh) + (size_t)(s & ((1 << sh) - 1));
+}
+
+// Ghost-map entries: s >= 0 copies cell s; -PROLONG_BASE <= s < 0 is the mean
+// of the 2x2x2 cells whose lowest is -s-1; s < -PROLONG_BASE names row
+// -s-PROLONG_BASE-1 of the prolongation table: {C, C-x, C+x, C-y, C+y, C-z,
+// C+z (each a copy or mean entry), side bits}, the coarse cell containing the
+// ghost cell, its neighbours at C's level, and bit a set when the ghost cell
+// is the upper half of C along axis a.
+constexpr int PROLONG_BASE = 1 << 30;
+constexpr int PROLONG_ROW = 8;
+
+// Field f (fields fs = E^3 apart) of a copy or mean entry.
+__device__ __forceinline__ double src_value(const double *U, int s, int f, int lg) {
+    const size_t fs = (size_t)1 << (3 * lg);
+    if (s >= 0) return U[src_offset(s, lg) + f * fs];
+    const double *qf = U + src_offset(-s - 1, lg) + f * fs;
+    const int E = 1 << lg, E2 = E * E;
+    double acc = 0.0;
+    acc = acc + qf[0];
+    acc = acc + qf[1];
+    acc = acc + qf[E];
+    acc = acc + qf[E + 1];
+    acc = acc + qf[E2];
+    acc = acc + qf[E2 + 1];
+    acc = acc + qf[E2 + E];
+    acc = acc + qf[E2 + E + 1];
+    return acc * 0.125;
+}
+
+__device__ __forceinline__ double minmod2(double a, double b) {
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+// Linear-limited prolongation of field f from a table row: U_C plus, axis by
+// axis in x, y, z order, (+-1/4) minmod(U_{C+e} - U_C, U_C - U_{C-e}).
+__device__ __forceinline__ double prolong_value(const double *U, const int32_t *row, int f, int lg) {
+    const double uc = src_value(U, row[0], f, lg);
+    double v = uc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double um = src_value(U, row[1 + 2 * a], f, lg);
+        const double up = src_value(U, row[2 + 2 * a], f, lg);
+        const double frac = ((row[7] >> a) & 1) ? 0.25 : -0.25;
+        v = v + frac * minmod2(up - uc, uc - um);
+    }
+    return v;
+}
+
+// Field f of whatever a ghost-map entry names; an out-of-range prolongation
+// row (a map used with the wrong table) gives NaN, which the stage reports.
+__device__ __forceinline__ double ghost_value(const double *U, int s, int f, int lg, const int32_t *prolong,
+                                              int n_prolong) {
+    if (s >= -PROLONG_BASE) return src_value(U, s, f, lg);
+    const int r = -s - PROLONG_BASE - 1;
+    if (!prolong || r >= n_prolong) return __builtin_nan("");
+    return prolong_value(U, prolong + (size_t)r * PROLONG_ROW, f, lg);
 }
 
 // Boundary faces of a leaf: f = 2 axis + side (side 1 = +axis); the 64 face
@@ -137,7 +197,7 @@ hipError_t hydro_launch_reflux(const hydro::RefluxArgs &r, int n_entries, hipStr
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, int ts, double cfl,
                            double *dt_out, hipStream_t s);
 hipError_t hydro_launch_amax_leaves(const double *blk, int ts, int n, double *out, hipStream_t s);
-hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,
-                              uint8_t *valid, hipStream_t s);
-hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,
-                                    hipStream_t s);
+hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, const int32_t *prolong, int n_prolong,
+                              int n, float *X, float *T, uint8_t *valid, hipStream_t s);
+hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, const int32_t *prolong,
+                                    int n_prolong, int n, double *out, hipStream_t s);

@@ -48,6 +48,8 @@ struct MlpInfer {
     unsigned long long *fb_count;  // cells that fell back to plain PPM
     int leaf0;                  // first block of the launch
     int ts, lg;                 // blocks per leaf (log2), leaf edge (log2)
+    const int32_t *prolong;     // linear-prolongation rows (or null)
+    int n_prolong;
 };
 
 }  // namespace mlp

@@ -455,6 +455,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) m
             const int gi = pp % PB - GW, gj = (pp / PB) % PB - GW, gk = pp / (PB * PB) - GW;
             if (gi < -2 || gi > 9 || gj < -2 || gj > 9 || gk < -2 || gk > 9) continue;
             const int src = gm[g];
+            if (src < -PROLONG_BASE) {
+                B12[p12(gi, gj, gk)] = ghost_value(m.U, src, f, m.lg, m.prolong, m.n_prolong);
+                continue;
+            }
             const int b = src >= 0 ? src : -src - 1;
             const double *qf = m.U + src_offset(b, m.lg) + f * fs;
             double v;

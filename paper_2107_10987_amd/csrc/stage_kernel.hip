@@ -240,7 +240,8 @@ __device__ __forceinline__ double wave_max(double v) {
 // 8^3 cells from U, its ghost cells through the ghost map (a copy, or the mean
 // of the 2x2x2 cells of a finer leaf, summed in z, y, x order).
 __device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm, int b,
-                                             int ts, int lg, int tid, int nt) {
+                                             int ts, int lg, const int32_t *prolong, int n_prolong,
+                                             int tid, int nt) {
     const double *Ub = U + block_base(b, ts, lg);
     const size_t fs = (size_t)1 << (3 * lg);
     for (int e = tid; e < LEAF_STRIDE; e += nt) {
@@ -256,6 +257,9 @@ __device__ __forceinline__ void gather_block(double *P, const double *U, const i
             const double *q = U + src_offset(src, lg);
 #pragma unroll
             for (int f = 0; f < NF; ++f) P[f * NP + p] = q[f * fs];
+        } else if (src < -PROLONG_BASE) {
+#pragma unroll 1
+            for (int f = 0; f < NF; ++f) P[f * NP + p] = ghost_value(U, src, f, lg, prolong, n_prolong);
         } else {
             const double *q = U + src_offset(-src - 1, lg);
 #pragma unroll
@@ -382,7 +386,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
 
-    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NT);
+    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NT);
     __syncthreads();
 
     double dx, org[3];
@@ -686,7 +690,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
-    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NTC);
+    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NTC);
     __syncthreads();
     const ColLane L(tid);
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
@@ -723,7 +727,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         if (item >= items) break;
         const int leaf = a.leaf0 + item / T;
         const int tile = item - (item / T) * T;
-        gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, tid, NTC);
+        gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NTC);
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
@@ -851,10 +855,11 @@ __global__ void __launch_bounds__(NTR) reflux_kernel(RefluxArgs r) {
 
 // Reconstructed values at the 26 points of every interior cell.
 __global__ void __launch_bounds__(NT) reconstruct_kernel(const double *U, const int32_t *gm,
+                                                         const int32_t *prolong, int n_prolong,
                                                          double *out) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, 0, 3, threadIdx.x, NT);
+    gather_block(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x, NT);
     __syncthreads();
     double *o = out + (size_t)leaf * NF * NC * 26;
     for (int e = threadIdx.x; e < NC * 26; e += NT) {
@@ -898,11 +903,12 @@ hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
 // one-hot id (X [.][34], FP32 of the FP64 values) and the plain PPM values at
 // the 26 points in the same normalisation (T [.][26]); rows are
 // [leaf][cell][field], and valid = 0 marks flat neighbourhoods (sigma = 0).
-__global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_t *gm, float *X,
+__global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_t *gm,
+                                                   const int32_t *prolong, int n_prolong, float *X,
                                                    float *T, uint8_t *valid) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, 0, 3, threadIdx.x, NT);
+    gather_block(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x, NT);
     __syncthreads();
     for (int e = threadIdx.x; e < NC * NF; e += NT) {
         const int c = e / NF, f = e - (e / NF) * NF;
@@ -936,10 +942,10 @@ __global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_
     }
 }
 
-hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, int n, float *X, float *T,
-                              uint8_t *valid, hipStream_t s) {
+hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, const int32_t *prolong, int n_prolong,
+                              int n, float *X, float *T, uint8_t *valid, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pairs_kernel, dim3(n), dim3(NT), 0, s, U, gm, X, T, valid);
+    hipLaunchKernelGGL(pairs_kernel, dim3(n), dim3(NT), 0, s, U, gm, prolong, n_prolong, X, T, valid);
     return hipGetLastError();
 }
 
@@ -998,9 +1004,9 @@ hipError_t hydro_launch_amax_leaves(const double *blk, int ts, int n, double *ou
     return hipGetLastError();
 }
 
-hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, int n, double *out,
-                                    hipStream_t s) {
+hipError_t hydro_launch_reconstruct(const double *U, const int32_t *gmap, const int32_t *prolong,
+                                    int n_prolong, int n, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reconstruct_kernel, dim3(n), dim3(NT), 0, s, U, gmap, out);
+    hipLaunchKernelGGL(reconstruct_kernel, dim3(n), dim3(NT), 0, s, U, gmap, prolong, n_prolong, out);
     return hipGetLastError();
 }

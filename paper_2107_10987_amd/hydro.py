@@ -18,7 +18,8 @@ OK, EINVAL, ENOMEM, EHIP, ENONPHYS = 0, -1, -2, -3, -4
 NX, NF, NC, NGHOST = 8, 7, 512, 2232
 REFLUX_ENTRY = 26
 
-EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_reflux_map", "hydro_step",
+EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_ghost_map_linear",
+           "hydro_reflux_map", "hydro_step",
            "hydro_stage",
            "hydro_signal_speed", "hydro_reconstruct", "hydro_step_dev", "hydro_dt",
            "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_mlp_load",
@@ -47,7 +48,7 @@ class Grid(C.Structure):
                 ("U", C.c_void_p), ("dx", C.c_void_p), ("origin", C.c_void_p),
                 ("ghost_map", C.c_void_p), ("omega", C.c_double), ("gamma", C.c_double),
                 ("stream", C.c_void_p), ("face_flags", C.c_void_p), ("reflux", C.c_void_p),
-                ("n_reflux", C.c_int32)]
+                ("n_reflux", C.c_int32), ("prolong", C.c_void_p), ("n_prolong", C.c_int32)]
 
 
 class Tree(C.Structure):
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_ghost_map.argtypes = [C.POINTER(Tree), C.POINTER(C.c_int32)]
     ip = C.POINTER(C.c_int32)
     L.hydro_reflux_map.argtypes = [C.POINTER(Tree), ip, ip, ip]
+    L.hydro_ghost_map_linear.argtypes = [C.POINTER(Tree), ip, ip, C.c_int32, ip]
     L.hydro_step.argtypes = [vp, C.POINTER(Grid), C.c_double, dp]
     L.hydro_stage.argtypes = [vp, C.POINTER(Grid), C.c_int, C.c_double, vp, vp, vp, vp]
     L.hydro_signal_speed.argtypes = [vp, C.POINTER(Grid), vp]
@@ -129,6 +131,26 @@ def ghost_map(tree) -> np.ndarray:
     return out
 
 
+def ghost_map_linear(tree):
+    """Ghost map with linear-limited prolongation from coarser leaves, and its
+    table of prolongation rows int32 [m][8], built by the library."""
+    L = load()
+    t, _keep = _tree_struct(tree)
+    shape = (tree.n, NGHOST) if tree.leaf_edge == NX else (tree.n, 8, NGHOST)
+    out = np.empty(shape, dtype=np.int32)
+    m = C.c_int32()
+    ip = C.POINTER(C.c_int32)
+    rc = L.hydro_ghost_map_linear(C.byref(t), out.ctypes.data_as(ip), None, 0, C.byref(m))
+    if rc not in (OK, ENOMEM):
+        raise HydroError(rc, L.hydro_last_error(None).decode())
+    table = np.empty((max(m.value, 1), 8), dtype=np.int32)
+    rc = L.hydro_ghost_map_linear(C.byref(t), out.ctypes.data_as(ip), table.ctypes.data_as(ip),
+                                  m.value, C.byref(m))
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
+    return out, table[:m.value].copy()
+
+
 def reflux_map(tree):
     """Coarse/fine face lists of a workloads.Tree, built by the library:
     (face_flags int32 [n], entries int32 [m][26])."""
@@ -158,7 +180,7 @@ class Hydro:
     def __init__(self, max_leaves: int, device: int = 0, eta1: float = 1e-3, eta2: float = 1e-1,
                  schedule: str = "auto", tune_cache: str | None = None, learned: bool = False,
                  mlp_batch: int = 4096, rk_order: int = 2, centre_only: bool = False,
-                 reflux: bool = False, leaf_edge: int = NX):
+                 reflux: bool = False, leaf_edge: int = NX, prolong: bool = False):
         import torch
         self.torch = torch
         self.L = load()
@@ -166,6 +188,7 @@ class Hydro:
         self.schedule = schedule
         self.learned = learned
         self.reflux = reflux
+        self.prolong = prolong          # grids get ghost maps with linear prolongation
         self.leaf_edge = int(leaf_edge)
         self.p = Params(int(max_leaves), int(device), int(bool(learned)), SCHEDULES[schedule],
                         float(eta1), float(eta2), tune_cache.encode() if tune_cache else None,
@@ -309,7 +332,16 @@ class DeviceGrid:
         assert tuple(self.U.shape) == (tree.n, NF, E, E, E)
         self.dx = torch.as_tensor(a["dx"], device=dev)
         self.origin = torch.as_tensor(a["origin"], device=dev)
-        gm = ghost_map(tree) if gmap is None else gmap
+        self.ptable, npro = None, 0
+        if gmap is not None:
+            gm = gmap
+        elif hy.prolong:
+            gm, tab = ghost_map_linear(tree)
+            npro = tab.shape[0]
+            if npro:
+                self.ptable = torch.as_tensor(tab, device=dev)
+        else:
+            gm = ghost_map(tree)
         self.gmap = torch.as_tensor(gm, device=dev)
         self.stream = stream
         if launch_off is not None:
@@ -328,4 +360,5 @@ class DeviceGrid:
         self.n_reflux = nr
         self.c = Grid(tree.n, nl, offp, _ptr(self.U), _ptr(self.dx), _ptr(self.origin),
                       _ptr(self.gmap), float(omega), float(gamma), s or None,
-                      _ptr(self.flags) or None, (_ptr(self.reflux) if nr else 0) or None, nr)
+                      _ptr(self.flags) or None, (_ptr(self.reflux) if nr else 0) or None, nr,
+                      _ptr(self.ptable) or None, npro)

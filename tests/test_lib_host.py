@@ -249,3 +249,78 @@ def test_split_octets_round_trip():
     perm = [key[tuple(c)] for c in t8.coord]
     assert np.array_equal(U8, a.U[perm])
     assert np.array_equal(t8.origin, a.tree.origin[perm]) and np.array_equal(t8.dx, a.tree.dx[perm])
+
+
+def _src_vals(flat, s, E):
+    """Field values [7, len(s)] of copy / mean entries s (host)."""
+    C = E ** 3
+    out = np.zeros((7, s.size))
+    cp = s >= 0
+    out[:, cp] = flat[s[cp] // C, :, s[cp] % C].T
+    b = -s[~cp] - 1
+    if b.size:
+        acc = np.zeros((7, b.size))
+        for off in (0, 1, E, E + 1, E * E, E * E + 1, E * E + E, E * E + E + 1):
+            acc = acc + flat[b // C, :, b % C + off].T
+        out[:, ~cp] = acc * 0.125
+    return out
+
+
+def _minmod(a, b):
+    return np.where(a * b > 0.0, np.where(np.abs(a) <= np.abs(b), a, b), 0.0)
+
+
+def _apply_linear(U, gm, table, E):
+    """Padded 14^3 blocks of every 8^3 tile from a ghost map with prolongation
+    rows, on the host ([tiles, 7, 14, 14, 14] in split_octets order)."""
+    n = U.shape[0]
+    T = (E // 8) ** 3
+    flat = U.reshape(n, 7, E ** 3)
+    gm = gm.reshape(n, T, -1)
+    r = np.arange(-3, 11)
+    K, J, I = np.meshgrid(r, r, r, indexing="ij")
+    ghost = ~((I >= 0) & (I < 8) & (J >= 0) & (J < 8) & (K >= 0) & (K < 8))
+    gidx = np.nonzero(ghost.ravel())[0]
+    P = np.zeros((n * T, 7, 14 ** 3))
+    for l in range(n):
+        for t in range(T):
+            ti, tj, tk = t & 1, (t >> 1) & 1, t >> 2
+            Pb = P[T * l + t]
+            Pb[:, ~ghost.ravel()] = U[l, :, 8 * tk:8 * tk + 8, 8 * tj:8 * tj + 8, 8 * ti:8 * ti + 8].reshape(7, 512)
+            s = gm[l, t]
+            plain = s >= -(1 << 30)
+            Pb[:, gidx[plain]] = _src_vals(flat, s[plain], E)
+            rows = table[-s[~plain] - (1 << 30) - 1]
+            if rows.size:
+                uc = _src_vals(flat, rows[:, 0], E)
+                v = uc.copy()
+                for a in range(3):
+                    um = _src_vals(flat, rows[:, 1 + 2 * a], E)
+                    up = _src_vals(flat, rows[:, 2 + 2 * a], E)
+                    frac = np.where((rows[:, 7] >> a) & 1, 0.25, -0.25)
+                    v = v + frac[None, :] * _minmod(up - uc, uc - um)
+                Pb[:, gidx[~plain]] = v
+    return P.reshape(n * T, 7, 14, 14, 14)
+
+
+@needs_lib
+@pytest.mark.parametrize("E,bc", [(8, (OUTFLOW,) * 3), (8, (PERIODIC, OUTFLOW, PERIODIC)),
+                                  (16, (PERIODIC,) * 3)])
+def test_linear_ghost_map_matches_oracle(oracle_mod, E, bc):
+    from paper_2107_10987_amd.workloads import split_octets, to_tiles8
+    ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / (2 * E),
+                 [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)], leaf_edge=E)
+    ls.refine(0, (0, 0, 0))
+    if ls.can_refine(1, (0, 0, 0)):
+        ls.refine(1, (0, 0, 0))
+    tree = ls.tree()
+    rng = np.random.default_rng(9)
+    U = rng.uniform(0.5, 2.0, size=(tree.n, 7, E, E, E))
+    gm, table = hydro.ghost_map_linear(tree)
+    assert table.shape[0] > 0 and table.shape[1] == 8
+    P = _apply_linear(U, gm, table, E)
+    t8 = split_octets(tree)
+    P8 = oracle_mod.Oracle(t8, 5 / 3, 0.0, prolong=True).padded(to_tiles8(U) if E == 16 else U)
+    assert np.array_equal(P, P8)
+    # the plain map is the same except in the prolongated cells
+    assert np.array_equal(hydro.ghost_map(tree)[gm >= -(1 << 30)], gm[gm >= -(1 << 30)])
