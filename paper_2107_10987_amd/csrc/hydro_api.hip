@@ -44,7 +44,6 @@ struct hydro_t {
     bool mlp_loaded = false;
     double *mlp_val = nullptr;     // [max_leaves][7][26][896]
     uint8_t *mlp_ok = nullptr;     // [max_leaves][896]
-    uint16_t *ghost_pad = nullptr; // [2232]
     unsigned long long *fb_count = nullptr;
     int64_t mlp_cells = 0;
     int64_t graph_mlp_cells = 0;   // cells the captured graph reconstructs per replay
@@ -87,17 +86,12 @@ std::vector<uint16_t> ghost_table() {
     return t;
 }
 
-// 12^3 index (cells -2..9 per axis) of each needed cell slot of the
-// learned reconstruction.
-std::vector<uint16_t> slot_table() {
-    std::vector<uint16_t> t(mlp::NSLOT, 0);
-    for (int k = -1; k <= NX; ++k)
-        for (int j = -1; j <= NX; ++j)
-            for (int i = -1; i <= NX; ++i) {
-                const int out = (i < 0 || i >= NX) + (j < 0 || j >= NX) + (k < 0 || k >= NX);
-                if (out > 1) continue;
-                t[mlp::slot_of(i, j, k)] = (uint16_t)(((k + 2) * 12 + (j + 2)) * 12 + (i + 2));
-            }
+// Ghost slot of each padded cell (-1 for interior cells), the inverse of
+// ghost_table().
+std::vector<int16_t> pad_ghost_table() {
+    std::vector<int16_t> t(NP, -1);
+    const std::vector<uint16_t> g = ghost_table();
+    for (int s = 0; s < NG; ++s) t[g[s]] = (int16_t)s;
     return t;
 }
 
@@ -110,8 +104,8 @@ hipError_t ensure_ghost_table(int dev) {
         std::vector<uint16_t> t = ghost_table();
         g_table_err[dev] = hydro_upload_ghost_table(t.data());
         if (g_table_err[dev] == hipSuccess) {
-            std::vector<uint16_t> st = slot_table();
-            g_table_err[dev] = hydro_mlp_upload_slots(st.data());
+            std::vector<int16_t> pg = pad_ghost_table();
+            g_table_err[dev] = hydro_mlp_upload_pad_ghost(pg.data());
         }
     });
     return g_table_err[dev];
@@ -278,9 +272,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             mlp::MlpInfer m;
             m.U = Uin;
             m.gmap = g->ghost_map;
-            m.ghost_pad = h->ghost_pad;
-            m.wb = h->mt.wb;
-            m.par = h->mt.par;
+            m.wbi = h->mt.wbi;
+            m.bi = h->mt.bi;
             m.val = h->mlp_val;
             m.cell_ok = h->mlp_ok;
             m.fb_count = h->fb_count;
@@ -423,6 +416,8 @@ hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
     if (e == hipSuccess) e = mlp_alloc(h, &t.grad, mlp::NPAR);
     if (e == hipSuccess) e = mlp_alloc(h, &t.wb, mlp::WB_SIZE);
     if (e == hipSuccess) e = mlp_alloc(h, &t.wbT, mlp::WBT_SIZE);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.wbi, mlp::WBI_SIZE);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.bi, mlp::BI_SIZE);
     if (e == hipSuccess) e = mlp_alloc(h, &t.xb, B * 64);
     if (e == hipSuccess) e = mlp_alloc(h, &t.a1, B * 64);
     if (e == hipSuccess) e = mlp_alloc(h, &t.a2, B * 64);
@@ -439,11 +434,6 @@ hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
     if (e == hipSuccess && h->p.recon == 1) {
         e = mlp_alloc(h, &h->mlp_val, nleaves * mlp::NSLOT * NF * 26);
         if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_ok, nleaves * mlp::NSLOT);
-        if (e == hipSuccess) e = mlp_alloc(h, &h->ghost_pad, (size_t)NG);
-        if (e == hipSuccess) {
-            std::vector<uint16_t> gt = ghost_table();
-            e = hipMemcpy(h->ghost_pad, gt.data(), sizeof(uint16_t) * NG, hipMemcpyHostToDevice);
-        }
     }
     return e;
 }

@@ -14,6 +14,12 @@ constexpr int P_W1 = 0, P_B1 = 2176, P_W2 = 2240, P_B2 = 6336, P_W3 = 6400, P_B3
 constexpr int WB_W1 = 0, WB_W2 = 4096, WB_W3 = 8192, WB_SIZE = 10240;
 // transposed copies for the backward pass: W2T[64][64], W3T[64][64]
 constexpr int WB_W2T = 0, WB_W3T = 4096, WBT_SIZE = 8192;
+// inference image (bf16): W1i[64][32] (the 27 neighbourhood inputs, zero
+// padded), W2i[64][64] and W3i[32][64] with permuted columns and rows; its
+// float32 biases: b1 per field (the one-hot input's weight folded in), b2, b3
+constexpr int NNB = 27;
+constexpr int WI_W1 = 0, WI_W2 = 2048, WI_W3 = 6144, WBI_SIZE = 8192;
+constexpr int BI_B1 = 0, BI_B2 = 448, BI_B3 = 512, BI_SIZE = 544;
 // cells whose reconstruction a leaf's fluxes need: 512 interior + 6 x 64
 // ghost cells sharing a face with the leaf
 constexpr int NSLOT = 896;
@@ -31,6 +37,8 @@ __host__ __device__ inline int slot_of(int i, int j, int k) {
 struct MlpTrain {
     float *par, *m, *v, *grad;          // [NPAR]
     uint16_t *wb, *wbT;                 // bf16 MFMA copies
+    uint16_t *wbi;                      // [WBI_SIZE] inference image
+    float *bi;                          // [BI_SIZE] inference biases
     uint16_t *xb, *a1, *a2, *dz1, *dz2; // [B][64] bf16
     float *z1, *z2, *dz1f, *dz2f;       // [B][64]
     float *y, *dy;                      // [B][32]
@@ -40,9 +48,8 @@ struct MlpTrain {
 struct MlpInfer {
     const double *U;            // [n][7][E^3]
     const int32_t *gmap;        // [blocks][2232]
-    const uint16_t *ghost_pad;  // [2232] padded index of each ghost slot
-    const uint16_t *wb;         // bf16 weights
-    const float *par;           // float32 parameters (biases)
+    const uint16_t *wbi;        // bf16 inference image
+    const float *bi;            // its float32 biases
     double *val;                // [blocks][7][26][896] limited point values (field, dir, slot)
     uint8_t *cell_ok;           // [blocks][896]
     unsigned long long *fb_count;  // cells that fell back to plain PPM
@@ -55,7 +62,7 @@ struct MlpInfer {
 }  // namespace mlp
 }  // namespace hydro
 
-hipError_t hydro_mlp_upload_slots(const uint16_t *slot_cell12);
+hipError_t hydro_mlp_upload_pad_ghost(const int16_t *pad_ghost);
 hipError_t hydro_mlp_launch_infer(const hydro::mlp::MlpInfer &m, int nleaf, hipStream_t s);
 hipError_t hydro_mlp_launch_pack(const hydro::mlp::MlpTrain &t, hipStream_t s);
 hipError_t hydro_mlp_launch_forward(const hydro::mlp::MlpTrain &t, const float *X, int B, hipStream_t s);
