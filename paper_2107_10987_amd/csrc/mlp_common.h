@@ -15,10 +15,11 @@ constexpr int WB_W1 = 0, WB_W2 = 4096, WB_W3 = 8192, WB_SIZE = 10240;
 // transposed copies for the backward pass: W2T[64][64], W3T[64][64]
 constexpr int WB_W2T = 0, WB_W3T = 4096, WBT_SIZE = 8192;
 // inference image (bf16): W1i[64][32] (the 27 neighbourhood inputs, zero
-// padded), W2i[64][64] and W3i[32][64] with permuted columns and rows; its
-// float32 biases: b1 per field (the one-hot input's weight folded in), b2, b3
+// padded), W2i[64][64] and W3i[32][64] with permuted columns and rows, as 16
+// MFMA operand fragments of 512 values; its float32 biases: b1 per field (the
+// one-hot input's weight folded in), b2, b3
 constexpr int NNB = 27;
-constexpr int WI_W1 = 0, WI_W2 = 2048, WI_W3 = 6144, WBI_SIZE = 8192;
+constexpr int WBI_SIZE = 8192;
 constexpr int BI_B1 = 0, BI_B2 = 448, BI_B3 = 512, BI_SIZE = 544;
 // cells whose reconstruction a leaf's fluxes need: 512 interior + 6 x 64
 // ghost cells sharing a face with the leaf

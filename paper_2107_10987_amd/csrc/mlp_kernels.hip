@@ -337,8 +337,8 @@ __device__ __forceinline__ int output_of(int o) {
 
 // bf16 copies of the weights: W1p[64][64], W2[64][64], W3p[32][64] and the
 // transposes used by the backward pass, W2T[64][64], W3T[64][64] (k = output);
-// the inference image W1i[64][32], W2i[64][64], W3i[32][64] and its biases
-// (the first layer's per field: the one-hot input's weight folded in).
+// the inference image (W1i, W2i, W3i as MFMA A-operand fragments) and its
+// biases (the first layer's per field: the one-hot input's weight folded in).
 __global__ void __launch_bounds__(256) mlp_pack(MlpTrain t) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= 64 * 64) return;
@@ -349,15 +349,20 @@ __global__ void __launch_bounds__(256) mlp_pack(MlpTrain t) {
     // transposes: W2T[h][k2] = W2[k2][h]; W3T[h][o] = W3[o][h] (o < 26, else 0)
     t.wbT[WB_W2T + i] = bf16_bits(t.par[P_W2 + k * HID + n]);
     t.wbT[WB_W3T + i] = bf16_bits(k < OUT ? t.par[P_W3 + k * HID + n] : 0.f);
-    // inference image
-    if (i < 64 * 32) {
-        const int u = i / 32, kk = i % 32;
-        t.wbi[WI_W1 + i] = bf16_bits(kk < NNB ? t.par[P_W1 + u * IN + kk] : 0.f);
-    }
-    t.wbi[WI_W2 + i] = bf16_bits(t.par[P_W2 + n * HID + hidden_of(k)]);
-    if (n < 32) {
-        const int o = output_of(n);
-        t.wbi[WI_W3 + i] = bf16_bits(o >= 0 ? t.par[P_W3 + o * HID + hidden_of(k)] : 0.f);
+    // inference image, fragment by fragment (see infer_frag)
+    for (int e = i; e < WBI_SIZE; e += 64 * 64) {
+        const int F = e >> 9, lane = (e >> 3) & 63, j = e & 7, r = lane & 15, kq = 8 * (lane >> 4) + j;
+        float w = 0.f;
+        if (F < 4) {                       // W1i, m-tile F
+            if (kq < NNB) w = t.par[P_W1 + (16 * F + r) * IN + kq];
+        } else if (F < 12) {               // W2i, m-tile (F - 4) / 2, k block (F - 4) % 2
+            const int mt = (F - 4) >> 1, kb = (F - 4) & 1;
+            w = t.par[P_W2 + (16 * mt + r) * HID + hidden_of(32 * kb + kq)];
+        } else {                           // W3i, end (F - 12) / 2, k block (F - 12) % 2
+            const int en = (F - 12) >> 1, kb = (F - 12) & 1, o = output_of(16 * en + r);
+            if (o >= 0) w = t.par[P_W3 + o * HID + hidden_of(32 * kb + kq)];
+        }
+        t.wbi[e] = bf16_bits(w);
     }
     if (i < NF * HID) {
         const int f = i / HID, u = i % HID;
@@ -387,6 +392,14 @@ __device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// A-operand fragment F of the inference image for this lane: fragments are
+// stored lane by lane (64 x 8 bf16, 1 KB), so a wave reads 1 KB of
+// consecutive LDS without bank conflicts.  F 0..3: W1i m-tile F; 4..11: W2i
+// m-tile (F-4)/2, k block (F-4)%2; 12..15: W3i end (F-12)/2, k block (F-12)%2.
+__device__ __forceinline__ v8bf infer_frag(const uint16_t *W, int F, int lane) {
+    return *(const v8bf *)(W + 512 * F + 8 * lane);
+}
+
 // The plain limiter and the FP64 check on one line of a row, on its two
 // predicted values R (at +d) and L (at -d): each value clamped between the
 // cell and its neighbour in that direction, the pair put through the PPM
@@ -394,45 +407,36 @@ __device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
 // non-negative X, the monotonicity conditions with a rounding slack of
 // 1e-13 |D| (|L| + |q| + |R|)).  Limiter and check only ever couple the two
 // ends of one line, so a row is processed line by line.  nbR / nbL are the
-// neighbours in those directions.  Returns whether the line passes.
+// neighbours in those directions.  Returns whether the line passes.  Written
+// without branches: min/max clamps (a NaN prediction, which they would turn
+// into a bound, fails explicitly) and selects for the constraint's cases.
 __device__ __forceinline__ bool limit_check_line(double qc, double nbR, double nbL, int f, double &R,
                                                  double &L) {
+    bool ok = (R == R) & (L == L);
+    const double loR = fmin(qc, nbR), hiR = fmax(qc, nbR);
+    const double loL = fmin(qc, nbL), hiL = fmax(qc, nbL);
+    double r = fmin(fmax(R, loR), hiR), l = fmin(fmax(L, loL), hiL);
     {
-        const double lo = qc < nbR ? qc : nbR, hi = qc < nbR ? nbR : qc;
-        R = (R < lo) ? lo : R;
-        R = (R > hi) ? hi : R;
+        const bool ext = (r - qc) * (qc - l) <= 0.0;
+        const double D = r - l, M6 = 6.0 * (qc - 0.5 * (l + r));
+        const double DM = D * M6, DD = D * D;
+        const bool lowL = DM > DD, lowR = !lowL & (DM < -DD);
+        const double ln = lowL ? 3.0 * qc - 2.0 * r : l;
+        const double rn = lowR ? 3.0 * qc - 2.0 * l : r;
+        l = ext ? qc : ln;
+        r = ext ? qc : rn;
     }
+    ok = ok & (r >= loR) & (r <= hiR) & (l >= loL) & (l <= hiL);
+    if (f == RHO || f == EGAS || f == TAU) ok = ok & (r > 0.0) & (l > 0.0);
+    if (f == SPC) ok = ok & (r >= 0.0) & (l >= 0.0);
     {
-        const double lo = qc < nbL ? qc : nbL, hi = qc < nbL ? nbL : qc;
-        L = (L < lo) ? lo : L;
-        L = (L > hi) ? hi : L;
+        const double D = r - l, M6 = 6.0 * (qc - 0.5 * (l + r)), DM = D * M6;
+        const double lim = D * D + 1e-13 * fabs(D) * (fabs(l) + fabs(qc) + fabs(r));
+        const bool mono = ((r - qc) * (qc - l) > 0.0) & !(DM > lim) & !(DM < -lim);
+        ok = ok & (((l == qc) & (r == qc)) | mono);
     }
-    if ((R - qc) * (qc - L) <= 0.0) {
-        L = qc;
-        R = qc;
-    } else {
-        const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
-        if (D * M6 > D * D)
-            L = 3.0 * qc - 2.0 * R;
-        else if (D * M6 < -(D * D))
-            R = 3.0 * qc - 2.0 * L;
-    }
-    bool ok = true;
-    {
-        const double lo = qc < nbR ? qc : nbR, hi = qc < nbR ? nbR : qc;
-        ok = ok && (R >= lo && R <= hi);
-    }
-    {
-        const double lo = qc < nbL ? qc : nbL, hi = qc < nbL ? nbL : qc;
-        ok = ok && (L >= lo && L <= hi);
-    }
-    if (f == RHO || f == EGAS || f == TAU) ok = ok && (R > 0.0) && (L > 0.0);
-    if (f == SPC) ok = ok && (R >= 0.0) && (L >= 0.0);
-    if (!(L == qc && R == qc)) {
-        const double D = R - L, M6 = 6.0 * (qc - 0.5 * (L + R));
-        const double lim = D * D + 1e-13 * fabs(D) * (fabs(L) + fabs(qc) + fabs(R));
-        ok = ok && ((R - qc) * (qc - L) > 0.0) && !(D * M6 > lim) && !(D * M6 < -lim);
-    }
+    R = r;
+    L = l;
     return ok;
 }
 
@@ -516,33 +520,25 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
         const double qc = bx[cb];
         double nv[8], sig = 0.0, lo = qc, hi = qc;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 8; ++j) {   // (fmax and fmin pass over a NaN)
             nv[j] = bx[cb + koff[j]];
-            const double a = fabs(nv[j] - qc);
-            sig = a > sig ? a : sig;
-            lo = nv[j] < lo ? nv[j] : lo;
-            hi = nv[j] > hi ? nv[j] : hi;
+            sig = fmax(sig, fabs(nv[j] - qc));
+            lo = fmin(lo, nv[j]);
+            hi = fmax(hi, nv[j]);
         }
-        {   // over the row's four lane groups
-            double o = shfl_xor_d(sig, 16);
-            sig = o > sig ? o : sig;
-            o = shfl_xor_d(sig, 32);
-            sig = o > sig ? o : sig;
-        }
+        // over the row's four lane groups
+        sig = fmax(sig, shfl_xor_d(sig, 16));
+        sig = fmax(sig, shfl_xor_d(sig, 32));
         const bool flat = !(sig > 0.0);
         // the network's error is a few percent of sigma: where the density
         // spans more than a factor 8 over the neighbourhood, the low side's
         // point values (and s / rho from them) would be off by order one
         bool ok = true;
         if (f == RHO) {
-            double o = shfl_xor_d(lo, 16);
-            lo = o < lo ? o : lo;
-            o = shfl_xor_d(lo, 32);
-            lo = o < lo ? o : lo;
-            o = shfl_xor_d(hi, 16);
-            hi = o > hi ? o : hi;
-            o = shfl_xor_d(hi, 32);
-            hi = o > hi ? o : hi;
+            lo = fmin(lo, shfl_xor_d(lo, 16));
+            lo = fmin(lo, shfl_xor_d(lo, 32));
+            hi = fmax(hi, shfl_xor_d(hi, 16));
+            hi = fmax(hi, shfl_xor_d(hi, 32));
             ok = flat || hi <= 8.0 * lo;
         }
         const double rs = flat ? 0.0 : 1.0 / sig;
@@ -563,7 +559,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
         v4f z[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            z[mt] = mfma32(*(const v8bf *)(Wt + WI_W1 + (16 * mt + r) * 32 + 8 * q), x,
+            z[mt] = mfma32(infer_frag(Wt, mt, lane), x,
                            *(const v4f *)(bt + BI_B1 + HID * f + 16 * mt + 4 * q));
         v8bf h[2];
 #pragma unroll
@@ -574,7 +570,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
             v4f c = *(const v4f *)(bt + BI_B2 + 16 * mt + 4 * q);
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
-                c = mfma32(*(const v8bf *)(Wt + WI_W2 + (16 * mt + r) * 64 + 32 * kb + 8 * q), h[kb], c);
+                c = mfma32(infer_frag(Wt, 4 + 2 * mt + kb, lane), h[kb], c);
             z[mt] = c;
         }
 #pragma unroll
@@ -586,7 +582,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
             v4f c = *(const v4f *)(bt + BI_B3 + 16 * e + 4 * q);
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
-                c = mfma32(*(const v8bf *)(Wt + WI_W3 + (16 * e + r) * 64 + 32 * kb + 8 * q), h[kb], c);
+                c = mfma32(infer_frag(Wt, 12 + 2 * e + kb, lane), h[kb], c);
             y[e] = c;
         }
         // this lane's lines: denormalise, limit, check, store
