@@ -60,15 +60,10 @@ __device__ __forceinline__ double mc_half_slope(double qm, double q0, double qp)
     return (dl * dr > 0.0) ? copysign(m, d) : 0.0;
 }
 
-// PPM on the five values q(c + m*st), m = -2..2, with the CW84 limiter:
-// left (-st end) and right (+st end) interface values of the middle cell.
-__device__ __forceinline__ void ppm_both(const double *q, int c, int st, double &left,
-                                         double &right) {
-    const double q0 = q[c - 2 * st];
-    const double q1 = q[c - st];
-    const double q2 = q[c];
-    const double q3 = q[c + st];
-    const double q4 = q[c + 2 * st];
+// PPM on five values q0..q4 along a line, with the CW84 limiter: left (toward
+// q1) and right (toward q3) interface values of the middle cell.
+__device__ __forceinline__ void ppm_vals(double q0, double q1, double q2, double q3, double q4,
+                                         double &left, double &right) {
     const double third = 1.0 / 3.0;
     const double sm = mc_half_slope(q0, q1, q2);
     const double s0 = mc_half_slope(q1, q2, q3);
@@ -93,6 +88,13 @@ __device__ __forceinline__ void ppm_both(const double *q, int c, int st, double 
         left = L;
         right = R;
     }
+}
+
+// PPM on the five values q(c + m*st), m = -2..2: left (-st end) and right
+// (+st end) interface values of the middle cell.
+__device__ __forceinline__ void ppm_both(const double *q, int c, int st, double &left,
+                                         double &right) {
+    ppm_vals(q[c - 2 * st], q[c - st], q[c], q[c + st], q[c + 2 * st], left, right);
 }
 
 // Value at the +st end when `plus`, else at the -st end.
@@ -465,15 +467,32 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
     const bool plus = (dx != 0) ? (dx > 0) : ((dy != 0) ? (dy > 0) : (dz > 0));
     int st = dx * SX_ + dy * SY_ + dz * SZ_;
     st = plus ? st : -st;
+    const double *q = P + c;
+    double a0 = q[-2 * st], a1 = q[-st], a2 = q[0], a3 = q[st], a4 = q[2 * st];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
+        // the next field's stencil is loaded while this one is reconstructed
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0;
+        if (f + 1 < NF) {
+            const double *qn = q + (f + 1) * NP;
+            b0 = qn[-2 * st];
+            b1 = qn[-st];
+            b2 = qn[0];
+            b3 = qn[st];
+            b4 = qn[2 * st];
+        }
         double L, R;
-        ppm_both(P + f * NP, c, st, L, R);
+        ppm_vals(a0, a1, a2, a3, a4, L, R);
         pos[f] = plus ? R : L;
         neg[f] = plus ? L : R;
-        // keep the scheduler from hoisting every field's stencil loads at
-        // once: that costs ~70 VGPRs and forces spills at 11 waves per CU
+        // keep the scheduler from hoisting further fields' stencil loads:
+        // all seven at once cost ~70 VGPRs and force spills at 11 waves per CU
         __builtin_amdgcn_sched_barrier(0);
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
+        a3 = b3;
+        a4 = b4;
     }
 }
 
@@ -503,8 +522,17 @@ __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy
     }
 }
 
-__device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, 64); }
-__device__ __forceinline__ double shfl_down1(double v) { return __shfl_down(v, 1, 64); }
+// Whole-wave lane shifts by one (DPP wave_shr:1 / wave_shl:1, two 32-bit
+// moves, no LDS): lane l receives lane l - 1 (up) or l + 1 (down); lanes 0 and
+// 63, which have no source, keep their own value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double shfl_up1(double v) { return dpp_shift<0x138>(v); }
+__device__ __forceinline__ double shfl_down1(double v) { return dpp_shift<0x130>(v); }
 
 // Central-upwind flux at one face point of axis n, Simpson weight w added
 // into acc; returns the signal speed.
