@@ -430,6 +430,7 @@ hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
     if (e == hipSuccess) e = mlp_alloc(h, &t.y, B * 32);
     if (e == hipSuccess) e = mlp_alloc(h, &t.dy, B * 32);
     if (e == hipSuccess) e = mlp_alloc(h, &t.loss_rows, B);
+    if (e == hipSuccess) e = mlp_alloc(h, &t.gpart, (size_t)mlp::WG_SLICES * mlp::NPAR);
     if (e == hipSuccess) e = mlp_alloc(h, &h->fb_count, 1);
     if (e == hipSuccess && h->p.recon == 1) {
         e = mlp_alloc(h, &h->mlp_val, nleaves * mlp::NSLOT * NF * 26);

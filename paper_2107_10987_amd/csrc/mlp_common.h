@@ -19,6 +19,9 @@ constexpr int WB_W2T = 0, WB_W3T = 4096, WBT_SIZE = 8192;
 // MFMA operand fragments of 512 values; its float32 biases: b1 per field (the
 // one-hot input's weight folded in), b2, b3
 constexpr int NNB = 27;
+// weight-gradient reduction: 36 MFMA tiles (W3 2 x 4, W2 4 x 4, W1 4 x 3) per
+// batch slice
+constexpr int WG_TILES = 36, WG_SLICES = 16;
 constexpr int WBI_SIZE = 8192;
 constexpr int BI_B1 = 0, BI_B2 = 448, BI_B3 = 512, BI_SIZE = 544;
 // cells whose reconstruction a leaf's fluxes need: 512 interior + 6 x 64
@@ -44,6 +47,7 @@ struct MlpTrain {
     float *z1, *z2, *dz1f, *dz2f;       // [B][64]
     float *y, *dy;                      // [B][32]
     float *loss_rows;                   // [B]
+    float *gpart;                       // [WG_SLICES][NPAR] per-slice gradients
 };
 
 struct MlpInfer {

@@ -217,13 +217,17 @@ __global__ void __launch_bounds__(256) mlp_train_backward_rows(MlpTrain t, const
             }
 }
 
-// Weight gradients dW[m][n] = sum_b dZ[b][m] A[b][n] by MFMA, one wave per
-// 16x16 tile, reducing over all B rows in a fixed order (deterministic);
-// bias gradients by lanes summing columns of the FP32 dZ in row order.
-// Tiles: W3 (26x64 -> 2x4), W2 (4x4), W1 (64x34 -> 4x3 of the padded 64x48).
+// Weight and bias gradients, summed over the batch in a fixed order: the
+// batch is cut into WG_SLICES slices of whole 16-row blocks; workgroup
+// (slice, tile) reduces its slice for one 16 x 16 tile of one weight matrix on
+// MFMA (and, for the first tile of a row block, the bias sums) into the
+// slice's partial vector; mlp_grad_reduce then adds the slices in order.
 __global__ void __launch_bounds__(64) mlp_train_wgrad(MlpTrain t, int B) {
     const int lane = threadIdx.x;
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x % WG_TILES, slice = blockIdx.x / WG_TILES;
+    const int per = (B + 16 * WG_SLICES - 1) / (16 * WG_SLICES) * 16;
+    const int r0 = slice * per, r1 = min(B, r0 + per);
+    float *gp = t.gpart + (size_t)slice * NPAR;
     const uint16_t *dZ, *A;
     int mt, nt, ldz, gofs, mrows, ncols;
     if (tile < 8) {            // W3: dZ = dY (bf16 copy), A = a2
@@ -235,13 +239,13 @@ __global__ void __launch_bounds__(64) mlp_train_wgrad(MlpTrain t, int B) {
     }
     const int r = lane & 15, q = lane >> 4;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int b0 = 0; b0 < B; b0 += 16) {
+    for (int b0 = r0; b0 < r1; b0 += 16) {
         // A operand [m][k = batch]: dZ[b0 + 4q + i][16 mt + r]
         v4s a, bb;
         for (int i = 0; i < 4; ++i) {
             const int row = b0 + 4 * q + i;
             uint16_t va = 0, vb = 0;
-            if (row < B) {
+            if (row < r1) {
                 const int m = 16 * mt + r, n = 16 * nt + r;
                 if (m < mrows) va = dZ ? dZ[(size_t)row * ldz + m] : bf16_bits(t.dy[(size_t)row * 32 + m]);
                 vb = A[(size_t)row * 64 + n];
@@ -253,20 +257,29 @@ __global__ void __launch_bounds__(64) mlp_train_wgrad(MlpTrain t, int B) {
     }
     for (int i = 0; i < 4; ++i) {
         const int m = 16 * mt + 4 * q + i, n = 16 * nt + r;
-        if (m < mrows && n < ncols) t.grad[gofs + m * ncols + n] = acc[i];
+        if (m < mrows && n < ncols) gp[gofs + m * ncols + n] = acc[i];
     }
     // bias gradients: the first tile of each matrix's row block sums columns
     if (nt == 0 && lane < 16) {
         const int m = 16 * mt + lane;
         if (m < mrows) {
             float s = 0.f;
-            for (int b = 0; b < B; ++b)
+            for (int b = r0; b < r1; ++b)
                 s += (tile < 8) ? t.dy[(size_t)b * 32 + m]
                                 : (tile < 24 ? t.dz2f[(size_t)b * 64 + m] : t.dz1f[(size_t)b * 64 + m]);
             const int bofs = tile < 8 ? P_B3 : (tile < 24 ? P_B2 : P_B1);
-            t.grad[bofs + m] = s;
+            gp[bofs + m] = s;
         }
     }
+}
+
+// grad = the slices' partial gradients added in slice order.
+__global__ void __launch_bounds__(256) mlp_grad_reduce(MlpTrain t) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= NPAR) return;
+    float s = 0.f;
+    for (int sl = 0; sl < WG_SLICES; ++sl) s += t.gpart[(size_t)sl * NPAR + i];
+    t.grad[i] = s;
 }
 
 // Loss = sum of per-row partials / (B * 26), summed in row order.
@@ -638,7 +651,8 @@ hipError_t hydro_mlp_launch_forward(const MlpTrain &t, const float *X, int B, hi
 hipError_t hydro_mlp_launch_grad(const MlpTrain &t, const float *T, int B, float *loss, hipStream_t s) {
     const int waves = (B + 63) / 64;
     hipLaunchKernelGGL(mlp_train_backward_rows, dim3((waves + 3) / 4), dim3(256), 0, s, t, T, B);
-    hipLaunchKernelGGL(mlp_train_wgrad, dim3(8 + 16 + 12), dim3(64), 0, s, t, B);
+    hipLaunchKernelGGL(mlp_train_wgrad, dim3(WG_TILES * WG_SLICES), dim3(64), 0, s, t, B);
+    hipLaunchKernelGGL(mlp_grad_reduce, dim3((NPAR + 255) / 256), dim3(256), 0, s, t);
     if (loss) hipLaunchKernelGGL(mlp_loss_reduce, dim3(1), dim3(64), 0, s, t, B, loss);
     return hipGetLastError();
 }
