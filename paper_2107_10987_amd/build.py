@@ -1,8 +1,10 @@
 """Compile the gfx950 HIP hydro library in-tree with hipcc.
 
 Produces ``paper_2107_10987_amd/_build/libhydro.so``.  Every HIP source is
-compiled for gfx950 only, with FP contraction off (the stage arithmetic rounds
-exactly as written) and packed FP32 instructions disabled.
+compiled for gfx950 only, with packed FP32 instructions disabled and FP
+contraction off except in the blocks that enable it explicitly
+(``#pragma clang fp contract(fast)``: the PPM interface and constraint, the
+flux arithmetic after the dual-energy switch).
 """
 from __future__ import annotations
 
