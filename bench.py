@@ -121,9 +121,23 @@ def cpu_baseline(w, budget_s: float):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
+    # one host thread: stage 1 of the first 256 leaves of the final state
+    o1 = oracle.Oracle(w.tree, w.gamma, w.omega, threads=1)
+    n1, t1 = 256, time.perf_counter()
+    o1.stage(1, dt, U, l0=0, l1=n1)
+    el1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=w.cells * 2 * steps / el, unit="cell-updates/s", cores=threads, kind="oracle",
                 sample=f"{steps} full SSP-RK2 steps of the same 64^3 Sedov workload from t=0 "
-                       f"({w.n} leaves, {threads} host threads, {el:.1f} s)")
+                       f"({w.n} leaves, {threads} host threads, {el:.1f} s)",
+                single_thread={"value": n1 * 512 / el1, "unit": "cell-updates/s",
+                               "sample": f"stage 1 of {n1} leaves of the final state, 1 thread, {el1:.2f} s"},
+                host={"cpu_count": os.cpu_count(), "model": model})
 
 
 def train_network(torch, args):
@@ -194,7 +208,7 @@ def binary_leg(torch, args, params):
 def batched_legs(torch, args, params):
     """The 4096-leaf rotating polytrope on a 3-level octree, launched as seeded
     uneven batches with autotuned schedules: one SSP-RK2 step (two stages) at
-    the CFL time step, timed over repeats (median), plain PPM and the learned
+    the CFL time step, timed ten times after one untimed (median), plain PPM and the learned
     reconstruction with FP64 check and plain-PPM fallback."""
     from paper_2107_10987_amd.hydro import Hydro
     from paper_2107_10987_amd.workloads import rotating_polytrope, uneven_batches
@@ -215,7 +229,7 @@ def batched_legs(torch, args, params):
             table = t_ if table is None else table
             dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
             times = []
-            for r in range(6):
+            for r in range(11):
                 g.U.copy_(U0)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
