@@ -79,7 +79,7 @@ typedef struct hydro_params {
                            section IV-B); same reconstruction                      */
     int32_t reflux;     /* 1: flux correction at coarse/fine faces (every grid then
                            carries face_flags and the reflux list from
-                           hydro_reflux_map); 0: none.  8^3 leaves only.           */
+                           hydro_reflux_map); 0: none.                            */
     int32_t leaf_edge;  /* cells per leaf edge: 8 (0 = 8) or 16                     */
 } hydro_params;
 
@@ -95,7 +95,7 @@ typedef struct hydro_grid {
     double omega;              /* frame rotation rate about z                        */
     double gamma;              /* ratio of specific heats, > 1                       */
     void *stream;              /* hipStream_t; NULL = the null stream                */
-    const int32_t *face_flags; /* device [n] from hydro_reflux_map, or NULL without  */
+    const int32_t *face_flags; /* device [n T] from hydro_reflux_map, or NULL without */
     const int32_t *reflux;     /*   reflux; device [n_reflux][26] correction list    */
     int32_t n_reflux;          /*   entries in the list (may be 0)                   */
     const int32_t *prolong;    /* device [n_prolong][8] from hydro_ghost_map_linear  */
@@ -150,17 +150,21 @@ int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, in
  * library uses the conservative correction: each stage, the flux through a
  * coarse face shared with four finer cells is replaced by the mean of those
  * cells' own Simpson face fluxes.
- *   face_flags[t->n]: bit f (f = 2 axis + side, side 1 = the +axis face) set
- *     when face f of the leaf borders leaves one level finer (the leaf is
- *     corrected), bit 8+f when it borders a coarser leaf (the leaf's flux
+ * The lists are per 8^3 block: a leaf itself for 8^3 leaves; for 16^3 leaves
+ * block b = 8 leaf + t is the leaf's octant at cell offset
+ * 8 (t & 1, (t >> 1) & 1, t >> 2), and the lists are those of the mesh of
+ * octants (the same cells and levels), T = 8 blocks per leaf (T = 1 for 8^3).
+ *   face_flags[t->n * T]: bit f (f = 2 axis + side, side 1 = the +axis face)
+ *     set when face f of the block borders blocks one level finer (the block
+ *     is corrected), bit 8+f when it borders a coarser one (the block's flux
  *     through face f is kept for its coarse neighbour).
- *   entries[t->n][26] (capacity): one entry per corrected leaf, *n_entries of
- *     them: {leaf, mask of bits 0-5, child[6][4]}; child[f][o1 + 2 o2] is the
- *     finer leaf across face f whose offsets along the two other axes (in
- *     increasing axis order) are o1, o2; -1 for faces without finer leaves.
- * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face, a
- * leaf is outside the box, or the leaves are 16^3.  Synchronous; needs no
- * handle and no GPU. */
+ *   entries[t->n * T][26] (capacity): one entry per corrected block,
+ *     *n_entries of them: {block, mask of bits 0-5, child[6][4]};
+ *     child[f][o1 + 2 o2] is the finer block across face f whose offsets along
+ *     the two other axes (in increasing axis order) are o1, o2; -1 for faces
+ *     without finer blocks.
+ * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face or a
+ * leaf is outside the box.  Synchronous; needs no handle and no GPU. */
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries);
 
 /* One full SSP Runge-Kutta step of all leaves, in place on g->U (Shu-Osher

@@ -123,7 +123,7 @@ int check_grid(hydro_t *h, const hydro_grid *g) {
     if (!isfinite(g->omega)) return fail(h, HYDRO_EINVAL, "omega must be finite");
     if (h->p.reflux) {
         if (!g->face_flags) return fail(h, HYDRO_EINVAL, "reflux needs g->face_flags (hydro_reflux_map)");
-        if (g->n_reflux < 0 || g->n_reflux > g->n) return fail(h, HYDRO_EINVAL, "n_reflux out of range");
+        if (g->n_reflux < 0 || g->n_reflux > (g->n << h->ts)) return fail(h, HYDRO_EINVAL, "n_reflux out of range");
         if (g->n_reflux > 0 && !g->reflux) return fail(h, HYDRO_EINVAL, "reflux list is NULL");
     } else if (g->face_flags || g->n_reflux) {
         return fail(h, HYDRO_EINVAL, "grid carries reflux lists but the handle was created without reflux");
@@ -308,6 +308,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         r.last = a.last;
         r.ph = a.ph;
         r.status = h->status;
+        r.ts = h->ts;
+        r.lg = h->lg;
         hipError_t e = hydro_launch_reflux(r, g->n_reflux, s);
         if (e != hipSuccess) return hip_fail(h, e, "reflux launch");
     }
@@ -574,8 +576,6 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (p->reflux != 0 && p->reflux != 1) return fail(nullptr, HYDRO_EINVAL, "reflux must be 0 or 1");
     if (p->leaf_edge != 0 && p->leaf_edge != 8 && p->leaf_edge != 16)
         return fail(nullptr, HYDRO_EINVAL, "leaf_edge must be 8 or 16");
-    if (p->leaf_edge == 16 && p->reflux)
-        return fail(nullptr, HYDRO_EINVAL, "the coarse/fine flux correction supports 8^3 leaves only");
     if ((int64_t)p->max_leaves * (p->leaf_edge == 16 ? 4096 : 512) > INT32_MAX)
         return fail(nullptr, HYDRO_EINVAL, "max_leaves too large for int32 cell ids");
     if (p->schedule < HYDRO_SCHED_AUTO || p->schedule > HYDRO_SCHED_TILED)
@@ -989,8 +989,30 @@ int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, in
 
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries) {
     if (!face_flags || !entries || !n_entries) return fail(nullptr, HYDRO_EINVAL, "null output");
-    if (t && t->leaf_edge == 16)
-        return fail(nullptr, HYDRO_EINVAL, "the coarse/fine flux correction supports 8^3 leaves only");
+    if (t && t->leaf_edge == 16) {
+        // a mesh of 16^3 leaves is, cell for cell, the mesh of their 8^3
+        // octants (block b = 8 leaf + t at offset 8 (t & 1, t >> 1 & 1, t >> 2)
+        // cells, same level on a base grid of twice as many 8^3 leaves), and
+        // the kernels work on those blocks: the lists are built there
+        if (!t->level || !t->coord) return fail(nullptr, HYDRO_EINVAL, "tree arrays are NULL");
+        if (t->n <= 0 || t->n > INT32_MAX / 8) return fail(nullptr, HYDRO_EINVAL, "bad leaf count");
+        std::vector<int32_t> lev((size_t)t->n * 8), crd((size_t)t->n * 24);
+        for (int i = 0; i < t->n; ++i)
+            for (int b = 0; b < 8; ++b) {
+                const size_t o = (size_t)i * 8 + b;
+                lev[o] = t->level[i];
+                crd[3 * o + 0] = 2 * t->coord[3 * (size_t)i + 0] + (b & 1);
+                crd[3 * o + 1] = 2 * t->coord[3 * (size_t)i + 1] + ((b >> 1) & 1);
+                crd[3 * o + 2] = 2 * t->coord[3 * (size_t)i + 2] + (b >> 2);
+            }
+        hydro_tree t8 = *t;
+        t8.n = t->n * 8;
+        for (int a = 0; a < 3; ++a) t8.nb[a] = 2 * t->nb[a];
+        t8.level = lev.data();
+        t8.coord = crd.data();
+        t8.leaf_edge = 8;
+        return hydro_reflux_map(&t8, face_flags, entries, n_entries);
+    }
     TreeIndex ti;
     int rc = ti.build(t);
     if (rc) return rc;

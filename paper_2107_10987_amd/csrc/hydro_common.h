@@ -161,16 +161,17 @@ constexpr int BFLUX_STRIDE = NBFACE * NF * NX * NX;   // doubles per leaf
 constexpr int REFLUX_ENTRY = 26;                      // {leaf, mask, child[6][4]}
 
 struct RefluxArgs {
-    double *U;                // [n][7][512] stage output, corrected in place
-    const double *bflux;      // [n][6][7][64]
-    const int32_t *entries;   // [m][26]
-    const double *dx;         // [n]
+    double *U;                // [n][7][E^3] stage output, corrected in place
+    const double *bflux;      // [blocks][6][7][64]
+    const int32_t *entries;   // [m][26], leaf and children are blocks
+    const double *dx;         // [n] per leaf
     double dt;
     const double *dt_dev;     // if set, dt is read from device memory
     double cb;                // weight of dt L in the stage combine
     int last;                 // last stage: tracer resync of the corrected cells
     Phys ph;
     Status *status;
+    int ts, lg;               // blocks per leaf (log2), leaf edge (log2)
 };
 
 enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };

@@ -829,8 +829,10 @@ __global__ void __launch_bounds__(NTR) reflux_kernel(RefluxArgs r) {
     const int f = tid >> 6, t12 = tid & 63;
     const int t1 = t12 & 7, t2 = t12 >> 3;
     const double dt = r.dt_dev ? *r.dt_dev : r.dt;
-    const double idx = 1.0 / r.dx[leaf];
-    double *Ul = r.U + (size_t)leaf * LEAF_STRIDE;
+    const double idx = 1.0 / r.dx[leaf >> r.ts];
+    // the entry's block (an 8^3 tile of a leaf of 2^lg cells per edge)
+    double *Ul = r.U + block_base(leaf, r.ts, r.lg);
+    const size_t fs = (size_t)1 << (3 * r.lg);
     for (int phi = 0; phi < NBFACE; ++phi) {
         if (!((mask >> phi) & 1)) continue;   // uniform over the workgroup
         const int n = phi >> 1, side = phi & 1;
@@ -847,22 +849,23 @@ __global__ void __launch_bounds__(NTR) reflux_kernel(RefluxArgs r) {
         const int i = (n == 0) ? cn : t1;
         const int j = (n == 1) ? cn : ((n == 0) ? t1 : t2);
         const int k = (n == 2) ? cn : t2;
-        double *u = Ul + (size_t)f * NC + (k * NX + j) * NX + i;
+        double *u = Ul + f * fs + block_cell((k * NX + j) * NX + i, r.lg);
         *u = *u + r.cb * (dt * dL);
         __syncthreads();
     }
     for (int c = tid; c < NC; c += NTR) {
         if (!corrected_cell(mask, c)) continue;
+        double *uc = Ul + block_cell(c, r.lg);
         double o[NF];
 #pragma unroll
-        for (int g = 0; g < NF; ++g) o[g] = Ul[(size_t)g * NC + c];
+        for (int g = 0; g < NF; ++g) o[g] = uc[g * fs];
         if (r.last) {
             const double rinv = 1.0 / o[RHO];
             const double ek = 0.5 * (o[SX] * o[SX] + o[SY] * o[SY] + o[SZ] * o[SZ]) * rinv;
             const double eint = o[EGAS] - ek;
             if (eint > r.ph.eta2 * o[EGAS]) {
                 o[TAU] = pow(eint, 1.0 / r.ph.gamma);
-                Ul[(size_t)TAU * NC + c] = o[TAU];
+                uc[TAU * fs] = o[TAU];
             }
         }
         bool bad = !(o[RHO] > 0.0);
@@ -874,8 +877,9 @@ __global__ void __launch_bounds__(NTR) reflux_kernel(RefluxArgs r) {
                 badf = g;
             }
         if (bad && atomicCAS(&r.status->flag, 0, 1) == 0) {
-            r.status->leaf = leaf;
-            r.status->cell = c;
+            const int lf = leaf >> r.ts;
+            r.status->leaf = lf;
+            r.status->cell = (int)(uc - r.U - ((size_t)lf * NF << (3 * r.lg)));   // index within the leaf
             r.status->field = badf;
         }
     }

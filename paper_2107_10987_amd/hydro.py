@@ -152,12 +152,14 @@ def ghost_map_linear(tree):
 
 
 def reflux_map(tree):
-    """Coarse/fine face lists of a workloads.Tree, built by the library:
-    (face_flags int32 [n], entries int32 [m][26])."""
+    """Coarse/fine face lists of a workloads.Tree, built by the library, per
+    8^3 block (a leaf, or one of the eight octants of a 16^3 leaf):
+    (face_flags int32 [blocks], entries int32 [m][26])."""
     L = load()
     t, _keep = _tree_struct(tree)
-    flags = np.empty(tree.n, dtype=np.int32)
-    ent = np.empty((tree.n, REFLUX_ENTRY), dtype=np.int32)
+    nblk = tree.n * (tree.leaf_edge // NX) ** 3
+    flags = np.empty(nblk, dtype=np.int32)
+    ent = np.empty((nblk, REFLUX_ENTRY), dtype=np.int32)
     m = C.c_int32()
     ip = C.POINTER(C.c_int32)
     rc = L.hydro_reflux_map(C.byref(t), flags.ctypes.data_as(ip), ent.ctypes.data_as(ip), C.byref(m))

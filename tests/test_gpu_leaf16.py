@@ -1,4 +1,5 @@
-"""GPU parity of 16^3 leaves (eight 8^3 tiles each) against the CPU oracle.
+"""GPU parity of 16^3 leaves (eight 8^3 tiles each) against the CPU oracle,
+with and without the coarse/fine flux correction.
 
 A mesh of 16^3 leaves is cell for cell the mesh of 8^3 leaves obtained by
 splitting every leaf into its eight octants (same levels, same neighbours,
@@ -159,11 +160,55 @@ def test_learned_nan_network_16_is_the_plain_step(torch):
         lrn.close()
 
 
+@pytest.mark.parametrize("schedule", ["column", "face", "persistent", "tiled"])
+def test_reflux_16cubed_matches_oracle(torch, schedule):
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: 16^3 AMR with the coarse/fine flux correction, Omega 0.2, schedule {schedule}", flush=True)
+    t16 = _amr16()
+    U16 = _state(t16, seed=11)
+    o = oracle.Oracle(split_octets(t16), G, 0.2, reflux=True)
+    hy = Hydro(max_leaves=t16.n, leaf_edge=16, schedule=schedule, reflux=True)
+    try:
+        g = hy.grid(t16, torch.tensor(U16, device="cuda"), 0.2, G)
+        assert g.n_reflux > 0
+        U8 = to_tiles8(U16)
+        dt = o.dt(U8)
+        for s in range(2):
+            hy.step(g, dt)
+            U8, _ = o.step(dt, U8)
+            err = field_err(to_tiles8(g.U.cpu().numpy()), U8)
+            print(f"step {s} err", err, flush=True)
+            assert np.all(err <= TOL), err
+    finally:
+        hy.close()
+
+
+def test_reflux_16cubed_conserves(torch):
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: 16^3 AMR, flux correction and prolongation, totals over 4 steps", flush=True)
+    t16 = _amr16()
+    U16 = _state(t16, seed=12)
+    vol = t16.dx ** 3
+    tot0 = np.einsum("n,nf->f", vol, U16.reshape(t16.n, 7, -1).sum(axis=2))
+    scale = np.einsum("n,nf->f", vol, np.abs(U16).reshape(t16.n, 7, -1).sum(axis=2))
+    hy = Hydro(max_leaves=t16.n, leaf_edge=16, reflux=True, prolong=True)
+    try:
+        g = hy.grid(t16, torch.tensor(U16, device="cuda"), 0.0, G)
+        dt = float(0.4 * np.min(t16.dx / hy.signal_speed(g).cpu().numpy()))
+        for _ in range(4):
+            am = hy.step(g, dt)
+            dt = float(0.4 * np.min(t16.dx / am))
+        Ue = g.U.cpu().numpy()
+    finally:
+        hy.close()
+    err = np.abs(np.einsum("n,nf->f", vol, Ue.reshape(t16.n, 7, -1).sum(axis=2)) - tot0) / scale
+    print("relative total change", err, flush=True)
+    assert np.all(err[[0, 1, 2, 3, 4, 6]] <= 1e-14), err
+
+
 def test_leaf16_errors(torch):
     from paper_2107_10987_amd.hydro import EINVAL, Hydro, HydroError
-    with pytest.raises(HydroError) as e:
-        Hydro(max_leaves=8, leaf_edge=16, reflux=True)
-    assert e.value.code == EINVAL
     with pytest.raises(HydroError) as e:
         Hydro(max_leaves=8, leaf_edge=12)
     assert e.value.code == EINVAL

@@ -11,7 +11,7 @@ import pytest
 from paper_2107_10987_amd import hydro
 from paper_2107_10987_amd.build import LIB
 from paper_2107_10987_amd.workloads import (OUTFLOW, PERIODIC, LeafSet, blast_single_leaf,
-                                            rotating_polytrope, sedov_uniform, uniform_tree)
+                                            rotating_polytrope, sedov_uniform, split_octets, uniform_tree)
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hydro.h")
 
@@ -151,21 +151,23 @@ def _geometric_reflux(tree):
 
 
 @needs_lib
-@pytest.mark.parametrize("make", ["uniform", "amr_per", "amr_mixed", "polytrope"])
+@pytest.mark.parametrize("make", ["uniform", "amr_per", "amr_mixed", "polytrope", "amr16"])
 def test_reflux_map_matches_geometry(make):
     if make == "uniform":
         tree = uniform_tree((2, 2, 2), (PERIODIC,) * 3)
     elif make == "polytrope":
         tree = rotating_polytrope().tree
     else:
-        bc = (PERIODIC,) * 3 if make == "amr_per" else (OUTFLOW, PERIODIC, OUTFLOW)
-        ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / 16,
-                     [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)])
+        bc = (PERIODIC,) * 3 if make != "amr_mixed" else (OUTFLOW, PERIODIC, OUTFLOW)
+        E = 16 if make == "amr16" else 8
+        ls = LeafSet((2, 2, 2), bc, (0, 0, 0), 1 / (2 * E),
+                     [(0, i, j, k) for i in range(2) for j in range(2) for k in range(2)], leaf_edge=E)
         ls.refine(0, (0, 0, 0))
         ls.refine(0, (1, 1, 1))
         tree = ls.tree()
     flags, ent = hydro.reflux_map(tree)
-    want_flags, want = _geometric_reflux(tree)
+    # 16^3 leaves: per 8^3 block, the lists of the mesh of octants
+    want_flags, want = _geometric_reflux(split_octets(tree))
     assert np.array_equal(flags, want_flags)
     assert sorted(int(e[0]) for e in ent) == sorted(want)
     for e in ent:
