@@ -255,36 +255,62 @@ def batched_legs(torch, args, params):
     return out
 
 
+def timed_sedov(torch, hy, w, args):
+    """--warmup untimed device-dt steps, then two passes of exactly --steps
+    steps from the same initial state on one stream: eager launches with HIP
+    events around every stage launch (kernel-only time), and the whole job --
+    the signal-speed pre-pass for dt0, then the steps replayed from one HIP
+    graph -- between device synchronisations (end-to-end time).  Returns
+    (end-to-end seconds, event milliseconds, stage launches)."""
+    s = torch.cuda.Stream()
+    U0 = torch.tensor(w.U, device="cuda")
+    g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma, stream=s)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def reset():   # the initial state back in place (not part of the job)
+        with torch.cuda.stream(s):
+            g.U.copy_(U0)
+        s.synchronize()
+
+    def eager(nsteps):
+        reset()
+        hy.dt(g, w.cfl, dt_dev)   # dt0 from the signal-speed pre-pass, on the device
+        for _ in range(nsteps):
+            hy.step_dev(g, w.cfl, dt_dev)
+        s.synchronize()
+
+    eager(args.warmup)
+    hy.timing(True)
+    eager(args.steps)
+    kms, launches = hy.timing(False)
+    hy.check()   # deferred non-physical-state check
+    hy.graph_capture(g, w.cfl, dt_dev, args.steps)   # records the steps, runs nothing
+    reset()
+    hy.dt(g, w.cfl, dt_dev)
+    hy.graph_launch(s)                                # one untimed replay
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hy.dt(g, w.cfl, dt_dev)
+    hy.graph_launch(s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hy.check()
+    return el, kms, launches
+
+
 def leaf16_leg(torch, args):
     """The same 64^3 Sedov workload held as 64 leaves of 16^3 cells (the
     paper's production leaf size; each leaf is eight 8^3 tiles, one workgroup
-    each): --steps device-dt steps, stage-kernel time from HIP events."""
+    each), timed like the 8^3 leaves."""
     from paper_2107_10987_amd.hydro import Hydro
     from paper_2107_10987_amd.workloads import sedov_uniform
 
     w = sedov_uniform(4, leaf_edge=16)
     hy = Hydro(max_leaves=w.n, schedule=args.schedule, leaf_edge=16)
     try:
-        U0 = torch.tensor(w.U, device="cuda")
-        g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma)
-        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-
-        def run(nsteps, timed=False):
-            g.U.copy_(U0)
-            if timed:
-                hy.timing(True)
-            hy.dt(g, w.cfl, dt_dev)
-            for _ in range(nsteps):
-                hy.step_dev(g, w.cfl, dt_dev)
-
-        run(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run(args.steps, timed=True)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        kms, launches = hy.timing(False)
-        hy.check()
+        el, kms, launches = timed_sedov(torch, hy, w, args)
         avg = kms / 1e3 / max(launches, 1)
         return {"workload": "sedov-64^3 as 64 leaves of 16^3 cells (512 tiles of 8^3)",
                 "value": w.cells * 2 * args.steps / el, "unit": "cell-updates/s",
@@ -310,32 +336,9 @@ def main():
         sys.exit(1)
     w = sedov_uniform(8)
     hy = Hydro(max_leaves=w.n, schedule=args.schedule)
-    U0 = torch.tensor(w.U, device="cuda")
-    g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma)
-
-    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     if args.copy_probe_mib > 0:
         copy_probe(torch, args.copy_probe_mib)
-
-    def run(nsteps, timed=False):
-        # dt0 from the signal-speed pre-pass, then every step reads dt from
-        # and writes the next dt to device memory: no host round trip
-        g.U.copy_(U0)
-        if timed:   # the stage launches of the steps (the pre-pass is not timed)
-            hy.timing(True)
-        hy.dt(g, w.cfl, dt_dev)
-        for _ in range(nsteps):
-            hy.step_dev(g, w.cfl, dt_dev)
-
-    run(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps, timed=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kms, launches = hy.timing(False)
-    hy.check()   # deferred non-physical-state check of the timed steps
-    elapsed = t1 - t0
+    elapsed, kms, launches = timed_sedov(torch, hy, w, args)
     stages = 2 * args.steps
     value = w.cells * stages / elapsed
     avg_launch_s = kms / 1e3 / max(launches, 1)
