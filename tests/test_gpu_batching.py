@@ -160,3 +160,37 @@ def test_autotune_table_and_cache(torch, tmp_path):
     finally:
         hy2.close()
         ref.close()
+
+
+def test_bench_configuration_matches_oracle(torch):
+    # the timed configuration of the benchmark: 64^3 Sedov as 512 leaves,
+    # column walk, dt0 from the signal-speed pre-pass, then 20 SSP-RK2 steps
+    # with the time step on the device, replayed from one HIP graph on a
+    # non-default stream; the oracle runs the same 20 steps with its own dt
+    import oracle
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: sedov-64^3, 20 graph-replayed device-dt steps vs oracle", flush=True)
+    w = sedov_uniform(8)
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    hy = Hydro(max_leaves=w.n, schedule="column")
+    try:
+        s = torch.cuda.Stream()
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, stream=s)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hy.graph_capture(g, w.cfl, dt_dev, 20)
+        hy.dt(g, w.cfl, dt_dev)
+        hy.graph_launch(s)
+        s.synchronize()
+        hy.check()
+        U, dt = w.U.copy(), o.dt(w.U)
+        for _ in range(20):
+            U, am = o.step(dt, U)
+            dt = float(w.cfl * np.min(w.tree.dx / am))
+        got = g.U.cpu().numpy().reshape(w.n, 7, -1)
+        want = U.reshape(w.n, 7, -1)
+        err = np.array([np.abs(got[:, f] - want[:, f]).max() / np.abs(want[:, f]).max() for f in range(7)])
+        print("max rel err per field", err, "dt", dt_dev.item(), dt, flush=True)
+        assert np.all(err <= 1e-12), err
+        assert abs(dt_dev.item() - dt) <= 1e-12 * dt
+    finally:
+        hy.close()
