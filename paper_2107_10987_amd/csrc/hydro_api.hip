@@ -19,6 +19,8 @@
 
 using namespace hydro;
 
+constexpr int NSIDE = 3;   // side streams for the launches of a stage
+
 struct hydro_t {
     hydro_params p;
     int device;
@@ -27,7 +29,12 @@ struct hydro_t {
     int rk = 2;
     int ts = 0, lg = 3;        // 8^3 blocks per leaf (log2), leaf edge (log2)
     double *dscr = nullptr;    // column walk: [max_leaves][3][7][512]
-    int *queue = nullptr;      // persistent launches: [2]
+    int *queue = nullptr;      // persistent launches: [1 + NSIDE][2], one per stream
+    // the launches of one stage run on the caller's stream and NSIDE side
+    // streams (default priority), forked from and joined back to it by events
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[NSIDE] = {};
     int *leaf_done = nullptr;  // [max_leaves]
     double *tile_amax = nullptr;  // [max_leaves][3]
     double *bflux = nullptr;   // flux correction: [max_leaves][6][7][64]
@@ -259,6 +266,20 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
     const int nb = g->n_launch > 0 ? g->n_launch : 1;
+    // the launches of a stage read the same input and write disjoint blocks:
+    // they run concurrently on up to 1 + NSIDE streams (the caller's first),
+    // each with its own persistent-queue counters, and the caller's stream
+    // waits for all of them before anything that follows
+    int nonempty = 0;
+    for (int b = 0; b < nb; ++b)
+        nonempty += (g->n_launch > 0 ? g->launch_off[b + 1] - g->launch_off[b] : g->n) > 0;
+    const int nst = nonempty < 1 + NSIDE ? (nonempty > 0 ? nonempty : 1) : 1 + NSIDE;
+    if (nst > 1) {
+        hipError_t e = hipEventRecord(h->fork_ev, s);
+        for (int i = 0; i < nst - 1 && e == hipSuccess; ++i) e = hipStreamWaitEvent(h->side[i], h->fork_ev, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "stream fork");
+    }
+    int k = 0;   // non-empty launches so far
     for (int b = 0; b < nb; ++b) {
         // launches count 8^3 blocks: 2^ts per leaf
         const int l0 = g->n_launch > 0 ? g->launch_off[b] : 0;
@@ -266,6 +287,9 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         a.leaf0 = l0 << h->ts;
         a.nleaf = nl << h->ts;
         if (a.nleaf == 0) continue;
+        const int j = k++ % nst;
+        const hipStream_t st = j == 0 ? s : h->side[j - 1];
+        a.queue = h->queue + 2 * j;
         set_schedule(a, resolve_schedule(h, a.nleaf));
         if (h->p.recon == 1) {
             // the network's point values and per-cell verdicts for this launch
@@ -282,7 +306,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.lg = h->lg;
             m.prolong = g->prolong;
             m.n_prolong = g->n_prolong;
-            hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, s);
+            hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, st);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
             h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
             a.mlp_val = h->mlp_val;
@@ -290,10 +314,15 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             if (a.kernel == KERNEL_FACE) a.kernel = KERNEL_COLUMN;   // the face walk has no learned variant
         }
         const bool rec = allow_timing && h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
-        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], s);
-        hipError_t e = hydro_launch_stage(a, s);
+        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], st);
+        hipError_t e = hydro_launch_stage(a, st);
         if (e != hipSuccess) return hip_fail(h, e, "stage launch");
-        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used++ + 1], s);
+        if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used++ + 1], st);
+    }
+    for (int i = 0; i < nst - 1; ++i) {
+        hipError_t e = hipEventRecord(h->join_ev[i], h->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, h->join_ev[i], 0);
+        if (e != hipSuccess) return hip_fail(h, e, "stream join");
     }
     if (reflux && g->n_reflux > 0) {
         // after every launch of the stage: the finer leaves' fluxes are all kept
@@ -609,12 +638,17 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (e == hipSuccess && h->rk == 3) e = hipMalloc((void **)&h->U2, n * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->dscr, n * 3 * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->amax, n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * (1 + NSIDE) * sizeof(int));
+    for (int i = 0; i < NSIDE && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc((void **)&h->leaf_done, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->tile_amax, n * 3 * sizeof(double));
     if (e == hipSuccess && p->reflux) e = hipMalloc((void **)&h->bflux, n * BFLUX_STRIDE * sizeof(double));
     if (e == hipSuccess) e = alloc_mlp(h, n);
-    if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * (1 + NSIDE) * sizeof(int));
     if (e == hipSuccess) e = hipMemset(h->leaf_done, 0, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->status, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(h->status, 0, sizeof(Status));
@@ -635,6 +669,11 @@ int hydro_destroy(hydro_t *h) {
     if (!h) return HYDRO_OK;
     (void)hipSetDevice(h->device);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    for (int i = 0; i < NSIDE; ++i) {
+        if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
+        if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     if (h->U1) (void)hipFree(h->U1);
     if (h->U2) (void)hipFree(h->U2);
     if (h->amax) (void)hipFree(h->amax);
