@@ -83,7 +83,10 @@ typedef struct hydro_params {
     int32_t leaf_edge;  /* cells per leaf edge: 8 (0 = 8) or 16                     */
 } hydro_params;
 
-/* One set of leaves that exchange ghosts: the whole mesh of a step. */
+/* One set of leaves that exchange ghosts: the whole mesh of a step.  All work
+ * is ordered on `stream`: the launches of one stage may run concurrently on
+ * side streams of the handle, forked from `stream` and joined back to it before
+ * anything that follows. */
 typedef struct hydro_grid {
     int32_t n;                 /* leaves, 0 < n <= max_leaves                        */
     int32_t n_launch;          /* 0: one launch per stage; else launches over the   */
