@@ -208,7 +208,7 @@ def binary_leg(torch, args, params):
 def batched_legs(torch, args, params):
     """The 4096-leaf rotating polytrope on a 3-level octree, launched as seeded
     uneven batches with autotuned schedules: one SSP-RK2 step (two stages) at
-    the CFL time step, timed ten times after one untimed (median), plain PPM and the learned
+    the plain path's CFL time step, timed ten times after one untimed (median), plain PPM and the learned
     reconstruction with FP64 check and plain-PPM fallback."""
     from paper_2107_10987_amd.hydro import Hydro
     from paper_2107_10987_amd.workloads import rotating_polytrope, uneven_batches
@@ -227,7 +227,8 @@ def batched_legs(torch, args, params):
                 hy.mlp_load(params)
             t_ = hy.autotune(g)
             table = t_ if table is None else table
-            dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
+            if not on:   # both paths step with the plain path's CFL time step
+                dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
             times = []
             for r in range(11):
                 g.U.copy_(U0)
