@@ -26,7 +26,7 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// LDS staging of a wave's 64 rows: bf16 rows of 64 padded to a 68-element
+// Training kernels: LDS staging of a wave's 64 rows, bf16 rows of 64 padded to a 68-element
 // (136 B) stride, FP32 output rows of 32 padded to 34 (136 B).  Rows written
 // one per lane then fall in different banks, and the 8-byte MFMA operand
 // loads stay aligned.
