@@ -543,6 +543,18 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
         sig = fmax(sig, shfl_xor_d(sig, 16));
         sig = fmax(sig, shfl_xor_d(sig, 32));
         const bool flat = !(sig > 0.0);
+        if (__all(flat)) {
+            // sixteen flat cells (sigma = 0 in this field): every point value
+            // is the cell value, exactly, every row passes, and the network
+            // is not evaluated
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (4 * q + t >= 13) continue;
+                vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc;
+                vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc;
+            }
+            continue;
+        }
         // the network's error is a few percent of sigma: where the density
         // spans more than a factor 8 over the neighbourhood, the low side's
         // point values (and s / rho from them) would be off by order one
