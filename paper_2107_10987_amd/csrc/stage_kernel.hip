@@ -120,13 +120,38 @@ __device__ __forceinline__ void point_state(const double *P, int c, int dx, int 
     }
 }
 
+// Reciprocal and square root for the flux: the hardware estimates refined by
+// Newton steps (within an ulp of the correctly rounded results, a few
+// instructions instead of the IEEE sequences).  Valid states have positive
+// normal density and non-negative pressure (zero returns zero); where a
+// reconstructed state has zero or infinite density the refinement gives NaN
+// instead of an infinity, and the stage reports the non-physical result
+// either way.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    return x == 0.0 ? x : g;
+}
+
 // Euler flux along axis n (run-time) of one reconstructed state; returns |u_n| + c.
 // The dual-energy switch is evaluated without contraction, exactly as
 // written; the flux arithmetic after it may fuse multiply-adds.
 __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double xq, double yq,
                                                const Phys &ph, double F[NF]) {
     const double rho = U[RHO], E = U[EGAS], tau = U[TAU];
-    const double rinv = 1.0 / rho;
+    const double rinv = rcp_nr(rho);
     const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
@@ -139,7 +164,7 @@ __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double
         const double uy = v1 - ph.omega * xq;
         const double un = (n == 0) ? ux : ((n == 1) ? uy : v2);
         const double p = (ph.gamma - 1.0) * eint;
-        const double cs = sqrt(ph.gamma * p * rinv);
+        const double cs = sqrt_nr(ph.gamma * p * rinv);
         F[RHO] = rho * un;
         F[SX] = (n == 0) ? U[SX] * un + p : U[SX] * un;
         F[SY] = (n == 1) ? U[SY] * un + p : U[SY] * un;
@@ -156,7 +181,7 @@ template <int N>
 __device__ __forceinline__ double side_flux(const double U[NF], double xq, double yq,
                                             const Phys &ph, double F[NF]) {
     const double rho = U[RHO], E = U[EGAS], tau = U[TAU];
-    const double rinv = 1.0 / rho;
+    const double rinv = rcp_nr(rho);
     const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
     const double vn = (N == 0) ? v0 : ((N == 1) ? v1 : v2);
     // velocity relative to the grid rotating about z: u = v - omega x r
@@ -165,7 +190,7 @@ __device__ __forceinline__ double side_flux(const double U[NF], double xq, doubl
     double eint = E - ek;
     if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
     const double p = (ph.gamma - 1.0) * eint;
-    const double cs = sqrt(ph.gamma * p * rinv);
+    const double cs = sqrt_nr(ph.gamma * p * rinv);
     F[RHO] = rho * un;
     F[SX] = U[SX] * un;
     F[SY] = U[SY] * un;
