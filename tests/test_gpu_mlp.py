@@ -277,3 +277,29 @@ def test_learned_graph_replay_matches_eager_and_counts_cells(torch, trained):
     finally:
         eager.close()
         graph.close()
+
+
+def test_learned_uneven_launches_match_one_launch(torch, trained):
+    # the launches of a stage run concurrently on several streams, each with
+    # its own inference pre-pass: the result must not depend on the partition
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: learned path, 4 concurrent uneven launches vs one launch, sedov-32^3", flush=True)
+    w = sedov_uniform(4)
+    off = np.array([0, 3, 4, 20, 64], np.int32)
+    one = Hydro(max_leaves=w.n, schedule="column", learned=True)
+    many = Hydro(max_leaves=w.n, schedule="auto", learned=True)
+    try:
+        one.mlp_load(trained)
+        many.mlp_load(trained)
+        ga = one.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        gb = many.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        dt = 2e-4
+        for _ in range(3):
+            aa = one.step(ga, dt)
+            ab = many.step(gb, dt)
+            assert np.array_equal(aa, ab)
+        assert torch.equal(ga.U, gb.U)
+        assert one.mlp_stats() == many.mlp_stats()
+    finally:
+        one.close()
+        many.close()
