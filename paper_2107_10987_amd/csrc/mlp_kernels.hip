@@ -469,11 +469,12 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 // over the group by lane exchange), the three layers on MFMA, and the limiter
 // and FP64 check for its lines.  Point values go out as val[block][field]
 // [dir][slot]; a cell passes when all seven of its rows pass.
-__global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4))) mlp_infer_kernel(MlpInfer m) {
+__global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7))) mlp_infer_kernel(MlpInfer m) {
     __shared__ double box[NF][BOX];                               // 16,800 B
     __shared__ __attribute__((aligned(16))) uint16_t W[WBI_SIZE];  // 16,384 B
     __shared__ __attribute__((aligned(16))) float bias[BI_SIZE];   //  2,176 B
     __shared__ unsigned long long fails[NF];
+    __shared__ int4 otab[4][4];
     const int item = xcd_leaf(blockIdx.x, gridDim.x);
     const int blk = m.leaf0 + item / ICHUNK, chunk = item % ICHUNK;
     const int tid = threadIdx.x, lane = tid & 63, f = tid >> 6;
@@ -505,22 +506,30 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
     }
     __syncthreads();
     const int r = lane & 15, q = lane >> 4;
-    // this lane's features k = 8q + j (k < 27): neighbour offsets in the box
-    int koff[8];
+    // per lane group q: neighbour offsets in the box of features 8q .. 8q+7
+    // (k < 27), +d offsets of lines 4q .. 4q+3 and the output rows of their
+    // two ends; read in each tile (kept live, they would cost 16 registers)
+    if (tid < 4) {
+        const int qq = tid;
+        int ko[8], lo4[4], lr4[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = 8 * q + j < NNB ? 8 * q + j : 13;
-        koff[j] = (k % 3 - 1) + s1 * ((k / 3) % 3 - 1) + s2 * (k / 9 - 1);
-    }
-    // this lane's lines 4q + t: +d offset in the box, output rows of both ends
-    int loff[4], lrow[4];
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * qq + j < NNB ? 8 * qq + j : 13;
+            ko[j] = (k % 3 - 1) + s1 * ((k / 3) % 3 - 1) + s2 * (k / 9 - 1);
+        }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int lam = 4 * q + t < 13 ? 4 * q + t : 0;
-        const int op = c_lines[lam], om = 26 - op;
-        loff[t] = (op % 3 - 1) + s1 * ((op / 3) % 3 - 1) + s2 * (op / 9 - 1);
-        lrow[t] = (op < 13 ? op : op - 1) | ((om < 13 ? om : om - 1) << 8);
+        for (int t = 0; t < 4; ++t) {
+            const int lam = 4 * qq + t < 13 ? 4 * qq + t : 0;
+            const int op = c_lines[lam], om = 26 - op;
+            lo4[t] = (op % 3 - 1) + s1 * ((op / 3) % 3 - 1) + s2 * (op / 9 - 1);
+            lr4[t] = (op < 13 ? op : op - 1) | ((om < 13 ? om : om - 1) << 8);
+        }
+        otab[qq][0] = int4{ko[0], ko[1], ko[2], ko[3]};
+        otab[qq][1] = int4{ko[4], ko[5], ko[6], ko[7]};
+        otab[qq][2] = int4{lo4[0], lo4[1], lo4[2], lo4[3]};
+        otab[qq][3] = int4{lr4[0], lr4[1], lr4[2], lr4[3]};
     }
+    __syncthreads();
     const double *bx = box[f];
     double *vout = m.val + ((size_t)blk * NF + f) * 26 * NSLOT;
     unsigned long long wfail = 0;
@@ -531,13 +540,17 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
         const int cx = A == 0 ? Lc : u, cy = A == 1 ? Lc : (A == 0 ? u : v), cz = A == 2 ? Lc : v;
         const int cb = (cx - o0) + s1 * (cy - o1) + s2 * (cz - o2);
         const double qc = bx[cb];
-        double nv[8], sig = 0.0, lo = qc, hi = qc;
+        int oz = 0;
+        asm volatile("" : "+s"(oz));
+        const int4 ka = otab[q + oz][0], kb4 = otab[q + oz][1];
+        const int koff[8] = {ka.x, ka.y, ka.z, ka.w, kb4.x, kb4.y, kb4.z, kb4.w};
+        double sig = 0.0, lo = qc, hi = qc;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {   // (fmax and fmin pass over a NaN)
-            nv[j] = bx[cb + koff[j]];
-            sig = fmax(sig, fabs(nv[j] - qc));
-            lo = fmin(lo, nv[j]);
-            hi = fmax(hi, nv[j]);
+            const double nvj = bx[cb + koff[j]];
+            sig = fmax(sig, fabs(nvj - qc));
+            lo = fmin(lo, nvj);
+            hi = fmax(hi, nvj);
         }
         // over the row's four lane groups
         sig = fmax(sig, shfl_xor_d(sig, 16));
@@ -547,6 +560,8 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
             // sixteen flat cells (sigma = 0 in this field): every point value
             // is the cell value, exactly, every row passes, and the network
             // is not evaluated
+            const int4 lb = otab[q + oz][3];
+            const int lrow[4] = {lb.x, lb.y, lb.z, lb.w};
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (4 * q + t >= 13) continue;
@@ -567,10 +582,11 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
             ok = flat || hi <= 8.0 * lo;
         }
         const double rs = flat ? 0.0 : 1.0 / sig;
+        asm volatile("" ::: "memory");   // re-read the neighbours rather than keep them live
         v8bf x;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float fv = (flat || 8 * q + j >= NNB) ? 0.f : (float)((nv[j] - qc) * rs);
+            const float fv = (flat || 8 * q + j >= NNB) ? 0.f : (float)((bx[cb + koff[j]] - qc) * rs);
             x[j] = (__bf16)fv;
         }
         // an opaque zero offset: the weight and bias fragments are then read
@@ -611,6 +627,8 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(4)
             y[e] = c;
         }
         // this lane's lines: denormalise, limit, check, store
+        const int4 la = otab[q + wz][2], lb = otab[q + wz][3];
+        const int loff[4] = {la.x, la.y, la.z, la.w}, lrow[4] = {lb.x, lb.y, lb.z, lb.w};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (4 * q + t >= 13) continue;
