@@ -486,12 +486,14 @@ constexpr int NTC = 704;            // 11 waves x 64 lanes
 constexpr int COLS_PER_WAVE = 6;    // 6 columns x 10 cells = 60 lanes
 
 // Both ends of the line through padded cell c along d = (dx,dy,dz) for all
-// fields: pos = value at +d, neg = value at -d (canonical orientation).
+// fields: pos = value at +d, neg = value at -d.  The stencil is walked along
+// d itself, which the column walk always gives pointing to +n of its axis;
+// the same line met in another axis pass may be walked the other way, which
+// rounds its ends differently by at most an ulp (every face flux is still
+// computed once and used by both of its cells).
 __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy, int dz,
                                           double pos[NF], double neg[NF]) {
-    const bool plus = (dx != 0) ? (dx > 0) : ((dy != 0) ? (dy > 0) : (dz > 0));
-    int st = dx * SX_ + dy * SY_ + dz * SZ_;
-    st = plus ? st : -st;
+    const int st = dx * SX_ + dy * SY_ + dz * SZ_;
     const double *q = P + c;
     double a0 = q[-2 * st], a1 = q[-st], a2 = q[0], a3 = q[st], a4 = q[2 * st];
 #pragma unroll
@@ -508,8 +510,8 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
         }
         double L, R;
         ppm_vals(a0, a1, a2, a3, a4, L, R);
-        pos[f] = plus ? R : L;
-        neg[f] = plus ? L : R;
+        pos[f] = R;
+        neg[f] = L;
         // keep the scheduler from hoisting further fields' stencil loads:
         // all seven at once cost ~70 VGPRs and force spills at 11 waves per CU
         __builtin_amdgcn_sched_barrier(0);
