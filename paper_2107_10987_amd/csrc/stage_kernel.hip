@@ -158,17 +158,20 @@ __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double
     if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
     {
 #pragma clang fp contract(fast)
-        const double vn = (n == 0) ? v0 : ((n == 1) ? v1 : v2);
+        // axis n as weights 0 / 1 (uniform): sums in place of selects,
+        // adding exact zeros
+        const double ex = n == 0 ? 1.0 : 0.0, ey = n == 1 ? 1.0 : 0.0, ez = n == 2 ? 1.0 : 0.0;
+        const double vn = ex * v0 + ey * v1 + ez * v2;
         // velocity relative to the grid rotating about z: u = v - omega x r
         const double ux = v0 + ph.omega * yq;
         const double uy = v1 - ph.omega * xq;
-        const double un = (n == 0) ? ux : ((n == 1) ? uy : v2);
+        const double un = ex * ux + ey * uy + ez * v2;
         const double p = (ph.gamma - 1.0) * eint;
         const double cs = sqrt_nr(ph.gamma * p * rinv);
         F[RHO] = rho * un;
-        F[SX] = (n == 0) ? U[SX] * un + p : U[SX] * un;
-        F[SY] = (n == 1) ? U[SY] * un + p : U[SY] * un;
-        F[SZ] = (n == 2) ? U[SZ] * un + p : U[SZ] * un;
+        F[SX] = U[SX] * un + ex * p;
+        F[SY] = U[SY] * un + ey * p;
+        F[SZ] = U[SZ] * un + ez * p;
         F[EGAS] = E * un + p * vn;
         F[TAU] = tau * un;
         F[SPC] = U[SPC] * un;
