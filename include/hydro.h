@@ -220,8 +220,12 @@ int hydro_graph_launch(hydro_t *h, void *stream);
 /* Time every schedule on stage-1 launches of 1, 2, 4, ... leaves (up to
  * g->n, each bucket from the first leaves of g) and keep the fastest per
  * size bucket for HYDRO_SCHED_AUTO; table (host [HYDRO_NBUCKET], may be
- * NULL) receives it, and cache_path (may be NULL) a JSON copy.  Uses only
- * the handle's workspace; g->U is read, not written.  Synchronous. */
+ * NULL) receives it, and cache_path (may be NULL) a JSON copy.  When g has
+ * several launches per stage (which run concurrently), whole stages of that
+ * partition are also timed with the table and with each schedule for every
+ * launch, and a single schedule that is clearly faster is used for stages of
+ * several launches (kept in the JSON copy as "concurrent").  Uses only the
+ * handle's workspace; g->U is read, not written.  Synchronous. */
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
 
 /* ---- learned reconstruction ----------------------------------------------

@@ -40,6 +40,7 @@ struct hydro_t {
     double *bflux = nullptr;   // flux correction: [max_leaves][6][7][64]
     int num_cu = 0;
     int32_t table[HYDRO_NBUCKET];  // schedule per launch-size bucket (HYDRO_SCHED_AUTO)
+    int32_t multi_sched = -1;      // stages of several concurrent launches: one schedule for all (-1: table)
     bool table_loaded = false;
     std::string arch;
     hipGraph_t graph = nullptr;
@@ -205,8 +206,9 @@ int bucket_of(int nleaf) {
 }
 
 // Schedule of a launch of nleaf leaves.
-int resolve_schedule(const hydro_t *h, int nleaf) {
+int resolve_schedule(const hydro_t *h, int nleaf, bool concurrent) {
     if (h->p.schedule != HYDRO_SCHED_AUTO) return h->p.schedule;
+    if (concurrent && h->multi_sched >= 0) return h->multi_sched;
     if (h->table_loaded) return h->table[bucket_of(nleaf)];
     // built-in rule: spread small launches over (leaf, axis) tiles so they
     // still occupy most compute units; otherwise a workgroup per leaf
@@ -290,7 +292,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         const int j = k++ % nst;
         const hipStream_t st = j == 0 ? s : h->side[j - 1];
         a.queue = h->queue + 2 * j;
-        set_schedule(a, resolve_schedule(h, a.nleaf));
+        set_schedule(a, resolve_schedule(h, a.nleaf, nst > 1));
         if (h->p.recon == 1) {
             // the network's point values and per-cell verdicts for this launch
             mlp::MlpInfer m;
@@ -390,6 +392,16 @@ int load_table(hydro_t *h, const char *path) {
         while (pos < t.size() && (t[pos] == ',' || t[pos] == ' ' || t[pos] == '\n')) ++pos;
     }
     h->table_loaded = true;
+    h->multi_sched = -1;
+    const size_t c = t.find("\"concurrent\"");
+    if (c != std::string::npos) {
+        const size_t colon = t.find(':', c);
+        char *end = nullptr;
+        const long v = colon == std::string::npos ? -2 : strtol(t.c_str() + colon + 1, &end, 10);
+        if (v < -1 || v > HYDRO_SCHED_TILED || v == HYDRO_SCHED_AUTO)
+            return fail(h, HYDRO_EINVAL, "bad concurrent schedule in tune cache");
+        h->multi_sched = (int32_t)v;
+    }
     return HYDRO_OK;
 }
 
@@ -398,7 +410,7 @@ int save_table(hydro_t *h, const char *path) {
     if (!f) return fail(h, HYDRO_EINVAL, std::string("cannot write tune cache ") + path);
     f << "{\"arch\": \"" << h->arch << "\", \"schedule\": [";
     for (int b = 0; b < HYDRO_NBUCKET; ++b) f << (b ? ", " : "") << h->table[b];
-    f << "]}\n";
+    f << "], \"concurrent\": " << h->multi_sched << "}\n";
     return f.good() ? HYDRO_OK : fail(h, HYDRO_EINVAL, "tune cache write failed");
 }
 
@@ -818,6 +830,8 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(h, HYDRO_EHIP, "hipEventCreate");
     const int32_t saved_sched = h->p.schedule;
+    const bool saved_loaded = h->table_loaded;
+    const int32_t saved_multi = h->multi_sched;
     hydro_grid sub = *g;
     sub.n_launch = 0;
     sub.launch_off = nullptr;
@@ -847,11 +861,47 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
         h->table[b] = best;
         best_prev = best;
     }
+    // the grid's own partition: its launches run concurrently, where a small
+    // launch's latency hides behind the large ones and the chip's total work
+    // decides; time whole stages with the per-size table and with each
+    // schedule for every launch, keep the fastest
+    h->multi_sched = -1;
+    h->table_loaded = true;
+    if (rc == HYDRO_OK && g->n_launch > 1) {
+        hydro_grid part = *g;
+        part.n_reflux = 0;
+        h->p.schedule = HYDRO_SCHED_AUTO;
+        float best_ms = 1e30f;
+        int best = -1;
+        const int cand[4] = {-1, HYDRO_SCHED_COLUMN, HYDRO_SCHED_PERSISTENT, HYDRO_SCHED_TILED};
+        for (int ci = 0; ci < 4 && rc == HYDRO_OK; ++ci) {
+            h->multi_sched = cand[ci];
+            rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);   // warm
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && rc == HYDRO_OK; ++r)
+                rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = hip_fail(h, e, "autotune timing"); break; }
+            // the table is kept unless a single schedule is clearly faster
+            if (ci == 0 || ms < 0.98f * best_ms) {
+                best_ms = ms;
+                best = cand[ci];
+            }
+        }
+        h->multi_sched = best;
+    }
     h->p.schedule = saved_sched;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc) return rc;
-    h->table_loaded = true;
+    if (rc) {
+        h->table_loaded = saved_loaded;
+        h->multi_sched = saved_multi;
+        return rc;
+    }
     if (table) memcpy(table, h->table, sizeof(h->table));
     if (cache_path) return save_table(h, cache_path);
     return HYDRO_OK;

@@ -194,3 +194,37 @@ def test_bench_configuration_matches_oracle(torch):
         assert abs(dt_dev.item() - dt) <= 1e-12 * dt
     finally:
         hy.close()
+
+
+def test_autotune_concurrent_partition(torch, tmp_path):
+    # with several launches per stage the tuner also times whole stages of the
+    # grid's own partition and may pick one schedule for all of them; the
+    # choice is cached, and steps stay within the parity bound of the column walk
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: autotune on the polytrope's uneven partition", flush=True)
+    w = rotating_polytrope()
+    off = uneven_batches(w.n)
+    path = os.path.join(tmp_path, "tune.json")
+    hy = Hydro(max_leaves=w.n, schedule="auto")
+    try:
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        U_before = g.U.clone()
+        hy.autotune(g, path)
+        assert torch.equal(g.U, U_before)
+        doc = json.load(open(path))
+        print("concurrent schedule:", doc["concurrent"], flush=True)
+        assert doc["concurrent"] in (-1, 2, 3, 4)     # table, or column, persistent, tiled
+    finally:
+        hy.close()
+    tuned = Hydro(max_leaves=w.n, schedule="auto", tune_cache=path)
+    col = Hydro(max_leaves=w.n, schedule="column")
+    try:
+        ga = tuned.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        gb = col.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        dt = float(w.cfl * np.min(w.tree.dx / col.signal_speed(gb).cpu().numpy()))
+        tuned.step(ga, dt)
+        col.step(gb, dt)
+        assert np.all(_err(ga.U.cpu().numpy(), gb.U.cpu().numpy()) <= TOL)
+    finally:
+        tuned.close()
+        col.close()
