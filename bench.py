@@ -229,6 +229,8 @@ def batched_legs(torch, args, params):
             table = t_ if table is None else table
             if not on:   # both paths step with the plain path's CFL time step
                 dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
+            else:
+                hy.mlp_stats()   # count the fallbacks of the timed steps only
             times = []
             for r in range(11):
                 g.U.copy_(U0)
