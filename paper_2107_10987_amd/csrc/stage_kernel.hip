@@ -44,6 +44,26 @@ __device__ __forceinline__ int pidx(int i, int j, int k) {
 // kernel and spilled (a scratch write stream of ~170 B per lane per launch).
 __device__ __attribute__((noinline)) double pow_cold(double x, double y) { return pow(x, y); }
 
+// tau^gamma of the dual-energy switch, out of line like pow_cold.  For
+// gamma = 5/3 (the double nearest it), tau^(5/3) = tau^2 tau^(-1/3) with the
+// cube root by two Newton steps, y <- y (4 - a y^3) / 3, from a
+// single-precision estimate of a^(-1/3), where tau = m 2^e, e = 3k + r and
+// a = m 2^r in [0.5, 4): within a few ulp of the exact power, several times
+// cheaper than pow; other exponents and tau outside [2^-330, 2^330] take pow.
+__device__ __attribute__((noinline)) double pow_tau(double x, double g) {
+    if (g == 5.0 / 3.0 && x >= 0x1p-330 && x <= 0x1p+330) {
+        int e;
+        const double m = frexp(x, &e);
+        const int k = (e >= 0 ? e : e - 2) / 3;   // floor(e / 3)
+        const double a = ldexp(m, e - 3 * k);
+        double y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf((float)a) * (1.0f / 3.0f));
+        y = y * (4.0 - a * y * y * y) * (1.0 / 3.0);
+        y = y * (4.0 - a * y * y * y) * (1.0 / 3.0);
+        return x * x * ldexp(y, -k);
+    }
+    return pow(x, g);
+}
+
 // Monotonised-central slope of the middle value (zero at an extremum).
 // Half of it, computed as min(|q+ - q-| / 4, |dl|, |dr|) with the sign of the
 // centred difference: scaling by 2 commutes exactly with min, so this is the
@@ -155,7 +175,7 @@ __device__ __forceinline__ double side_flux_rt(int n, const double U[NF], double
     const double v0 = U[SX] * rinv, v1 = U[SY] * rinv, v2 = U[SZ] * rinv;
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
-    if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
+    if (eint < ph.eta1 * E) eint = pow_tau(tau, ph.gamma);
     {
 #pragma clang fp contract(fast)
         // axis n as weights 0 / 1 (uniform): sums in place of selects,
@@ -191,7 +211,7 @@ __device__ __forceinline__ double side_flux(const double U[NF], double xq, doubl
     const double un = (N == 0) ? (v0 + ph.omega * yq) : ((N == 1) ? (v1 - ph.omega * xq) : v2);
     const double ek = 0.5 * (U[SX] * U[SX] + U[SY] * U[SY] + U[SZ] * U[SZ]) * rinv;
     double eint = E - ek;
-    if (eint < ph.eta1 * E) eint = pow_cold(tau, ph.gamma);
+    if (eint < ph.eta1 * E) eint = pow_tau(tau, ph.gamma);
     const double p = (ph.gamma - 1.0) * eint;
     const double cs = sqrt_nr(ph.gamma * p * rinv);
     F[RHO] = rho * un;
