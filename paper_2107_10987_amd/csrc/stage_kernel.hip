@@ -289,19 +289,42 @@ __device__ __forceinline__ double wave_max(double v) {
 // Ghost-padded 14^3 block of block b into LDS (nt threads cooperate): its
 // 8^3 cells from U, its ghost cells through the ghost map (a copy, or the mean
 // of the 2x2x2 cells of a finer leaf, summed in z, y, x order).
+// Ghost-padded block of block b into LDS.  Each thread first issues all of
+// its interior loads, then all of its ghost-map reads, so the latencies
+// overlap instead of adding up loop iteration by loop iteration.
+template <int NTH>
 __device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm, int b,
                                              int ts, int lg, const int32_t *prolong, int n_prolong,
-                                             int tid, int nt) {
+                                             int tid) {
     const double *Ub = U + block_base(b, ts, lg);
     const size_t fs = (size_t)1 << (3 * lg);
-    for (int e = tid; e < LEAF_STRIDE; e += nt) {
+    constexpr int NI = (LEAF_STRIDE + NTH - 1) / NTH;
+    double v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = min(tid + i * NTH, LEAF_STRIDE - 1);   // (a clamped, in-bounds read)
         const int f = e >> 9, c = e & (NC - 1);
-        P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = Ub[f * fs + block_cell(c, lg)];
+        v[i] = Ub[f * fs + block_cell(c, lg)];
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + i * NTH;
+        const int f = e >> 9, c = e & (NC - 1);
+        if (e < LEAF_STRIDE) P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = v[i];
     }
     const int32_t *g = gm + (size_t)b * NG;
     const int E = 1 << lg, E2 = E * E;
-    for (int s = tid; s < NG; s += nt) {
-        const int src = g[s];
+    constexpr int NGI = (NG + NTH - 1) / NTH;
+    int srcs[NGI];
+#pragma unroll
+    for (int i = 0; i < NGI; ++i) {
+        srcs[i] = g[min(tid + i * NTH, NG - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < NGI; ++i) {
+        const int s = tid + i * NTH;
+        if (s >= NG) continue;
+        const int src = srcs[i];
         const int p = c_ghost_pad[s];
         if (src >= 0) {
             const double *q = U + src_offset(src, lg);
@@ -436,7 +459,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
 
-    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NT);
+    gather_block<NT>(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid);
     __syncthreads();
 
     double dx, org[3];
@@ -768,7 +791,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
-    gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NTC);
+    gather_block<NTC>(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid);
     __syncthreads();
     const ColLane L(tid);
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
@@ -805,7 +828,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         if (item >= items) break;
         const int leaf = a.leaf0 + item / T;
         const int tile = item - (item / T) * T;
-        gather_block(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid, NTC);
+        gather_block<NTC>(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid);
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
@@ -941,7 +964,7 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(const double *U, const 
                                                          double *out) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x, NT);
+    gather_block<NT>(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x);
     __syncthreads();
     double *o = out + (size_t)leaf * NF * NC * 26;
     for (int e = threadIdx.x; e < NC * 26; e += NT) {
@@ -990,7 +1013,7 @@ __global__ void __launch_bounds__(NT) pairs_kernel(const double *U, const int32_
                                                    float *T, uint8_t *valid) {
     __shared__ double P[NF * NP];
     const int leaf = blockIdx.x;
-    gather_block(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x, NT);
+    gather_block<NT>(P, U, gm, leaf, 0, 3, prolong, n_prolong, threadIdx.x);
     __syncthreads();
     for (int e = threadIdx.x; e < NC * NF; e += NT) {
         const int c = e / NF, f = e - (e / NF) * NF;
