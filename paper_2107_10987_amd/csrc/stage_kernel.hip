@@ -64,36 +64,36 @@ __device__ __attribute__((noinline)) double pow_tau(double x, double g) {
     return pow(x, g);
 }
 
-// Monotonised-central slope of the middle value (zero at an extremum).
-// Half of it, computed as min(|q+ - q-| / 4, |dl|, |dr|) with the sign of the
-// centred difference: scaling by 2 commutes exactly with min, so this is the
-// MC slope min(|q+ - q-| / 2, 2 |dl|, 2 |dr|) halved, bit for bit, without the
-// two doublings.  The interface formula takes it with 1/3 in place of 1/6
-// (fl(1/3) = 2 fl(1/6)), which again gives the same bits.
-__device__ __forceinline__ double mc_half_slope(double qm, double q0, double qp) {
+// Monotonised-central slope of the middle value (zero at an extremum),
+// computed as (sign dl + sign dr) min(|q+ - q-| / 4, |dl|, |dr|): scaling by
+// 2 commutes exactly with min, so 2 min(...) is min(|q+ - q-| / 2, 2 |dl|,
+// 2 |dr|) bit for bit, and the sign sum is +-2 where dl and dr agree and 0 at
+// an extremum (a zero difference makes the min zero), so neither the two
+// doublings nor a select are needed.
+__device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     const double dl = q0 - qm;
     const double dr = qp - q0;
     const double d = 0.25 * (qp - qm);
     // all three operands are finite and non-negative, so fmin (one FP64
     // instruction) selects exactly what the comparisons would
     const double m = fmin(fmin(fabs(d), fabs(dl)), fabs(dr));
-    return (dl * dr > 0.0) ? copysign(m, d) : 0.0;
+    return (copysign(1.0, dl) + copysign(1.0, dr)) * m;
 }
 
 // PPM on five values q0..q4 along a line, with the CW84 limiter: left (toward
 // q1) and right (toward q3) interface values of the middle cell.
 __device__ __forceinline__ void ppm_vals(double q0, double q1, double q2, double q3, double q4,
                                          double &left, double &right) {
-    const double third = 1.0 / 3.0;
-    const double sm = mc_half_slope(q0, q1, q2);
-    const double s0 = mc_half_slope(q1, q2, q3);
-    const double sp = mc_half_slope(q2, q3, q4);
+    const double sixth = 1.0 / 6.0;
+    const double sm = mc_slope(q0, q1, q2);
+    const double s0 = mc_slope(q1, q2, q3);
+    const double sp = mc_slope(q2, q3, q4);
     // the interface and constraint arithmetic may fuse multiply-adds (results
     // within an ulp or two of the uncontracted expressions)
     {
 #pragma clang fp contract(fast)
-        double R = q2 + 0.5 * (q3 - q2) - (sp - s0) * third;
-        double L = q1 + 0.5 * (q2 - q1) - (s0 - sm) * third;
+        double R = q2 + 0.5 * (q3 - q2) - (sp - s0) * sixth;
+        double L = q1 + 0.5 * (q2 - q1) - (s0 - sm) * sixth;
         if ((R - q2) * (q2 - L) <= 0.0) {
             L = q2;
             R = q2;
