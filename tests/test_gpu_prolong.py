@@ -168,3 +168,39 @@ def test_prolongation_learned_nan_network_is_the_plain_step(torch):
     finally:
         plain.close()
         lrn.close()
+
+
+def test_prolongation_reflux_graph_replay_uneven(torch):
+    # prolongation and flux correction over four concurrent uneven launches,
+    # captured in a HIP graph with the device time step: every replay equals
+    # the eager steps bit for bit
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: prolongation + reflux, 4 uneven launches, graph replay vs eager", flush=True)
+    t = _amr_tree()
+    U = _state(t, seed=21)
+    off = np.array([0, 2, 3, 11, t.n], np.int32)
+    he = Hydro(max_leaves=t.n, schedule="auto", reflux=True, prolong=True)
+    hg = Hydro(max_leaves=t.n, schedule="auto", reflux=True, prolong=True)
+    try:
+        s = torch.cuda.Stream()
+        ge = he.grid(t, torch.tensor(U, device="cuda"), 0.1, G, launch_off=off)
+        gg = hg.grid(t, torch.tensor(U, device="cuda"), 0.1, G, launch_off=off, stream=s)
+        dte = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        he.dt(ge, 0.4, dte)
+        hg.dt(gg, 0.4, dtg)
+        torch.cuda.synchronize()
+        hg.graph_capture(gg, 0.4, dtg, 2)
+        torch.cuda.synchronize()
+        for replay in range(3):
+            for _ in range(2):
+                he.step_dev(ge, 0.4, dte)
+            hg.graph_launch(s)
+            torch.cuda.synchronize()
+            _ = (ge.U.sum() + 1.0).item()        # unrelated eager work between replays
+            assert torch.equal(ge.U, gg.U), replay
+            assert dte.item() == dtg.item()
+    finally:
+        he.close()
+        hg.close()
