@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
 //
 // For axis n, the faces normal to n lie on 64 columns of cells along n.  A
 // column is held by 10 consecutive lanes, one per cell -1..8 along n (six
-// columns per wave, 11 waves per leaf).  For each of the nine lines through
+// columns per wave; the 192 columns of the three axes are 32 tasks for the
+// leaf's 12 waves).  For each of the nine lines through
 // a cell that cross a face of axis n (directions e_n + a t1 + b t2), a lane
 // runs PPM once and keeps both ends: the end pointing to -n serves the face
 // below the cell, and the end pointing to +n is passed one lane up to serve
@@ -528,7 +529,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageArgs a) {
 // work of a leaf, against 3x for one face per thread).
 // ---------------------------------------------------------------------------
 
-constexpr int NTC = 704;            // 11 waves x 64 lanes
+constexpr int NTC = 768;            // 12 waves x 64 lanes: three per SIMD
 constexpr int COLS_PER_WAVE = 6;    // 6 columns x 10 cells = 60 lanes
 
 // Both ends of the line through padded cell c along d = (dx,dy,dz) for all
@@ -559,7 +560,7 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
         pos[f] = R;
         neg[f] = L;
         // keep the scheduler from hoisting further fields' stencil loads:
-        // all seven at once cost ~70 VGPRs and force spills at 11 waves per CU
+        // all seven at once cost ~70 VGPRs and force spills at 12 waves per CU
         __builtin_amdgcn_sched_barrier(0);
         a0 = b0;
         a1 = b1;
@@ -700,26 +701,31 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     for (int f = 0; f < NF; ++f) dsum[f] = shfl_down1(acc[f]) - acc[f];
 }
 
-// Lane geometry of the column walk: column, cell -1..8, and whether the
-// lane holds a real column.
+// Lane geometry of the column walk.  A leaf's 3 x 64 columns are numbered
+// axis-major (column g walks axis g / 64); task t covers columns first + 6t ..
+// first + 6t + 5 of a range [first, first + count), one per ten lanes, so the
+// lanes of one wave may walk different axes.  Each lane gets its axis, column,
+// cell -1..8, and whether it holds a real column (the four spare lanes and
+// columns past the range reuse valid cells of the range's first column).
 struct ColLane {
-    int lane, wave, col, cell, c1, c2;
+    int axis, col, cell, c1, c2;
     bool live;
-    __device__ explicit ColLane(int tid) {
-        lane = tid & 63;
-        wave = tid >> 6;
+    __device__ ColLane(int lane, int t, int first, int count) {
         const int slot = lane / 10;
-        col = wave * COLS_PER_WAVE + slot;
-        live = slot < COLS_PER_WAVE && col < NX * NX;
-        col = live ? col : 0;
-        cell = lane - 10 * slot - 1;   // idle lanes reuse a valid cell of column 0
+        int g = first + t * COLS_PER_WAVE + slot;
+        live = slot < COLS_PER_WAVE && g < first + count;
+        g = live ? g : first;
+        axis = g / (NX * NX);
+        col = g - axis * NX * NX;
+        cell = lane - 10 * slot - 1;
         c1 = col & 7;
         c2 = col >> 3;
     }
 };
 
-// Flux differences of one axis of one leaf into its workspace slice W
-// (linear cell index); returns this lane's signal speed maximum.
+// Flux differences along this lane's axis N of one leaf into that axis's
+// workspace slice of W (linear cell index); folds the lane's signal speeds
+// into smax.
 __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const double *P,
                                                const ColLane &L, int leaf, double *W, double &smax) {
     double dx, ox, oy, oz;
@@ -734,39 +740,6 @@ __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const 
                                : (L.cell * NX + L.c2) * NX + L.c1;
 #pragma unroll
         for (int f = 0; f < NF; ++f) W[(N * NF + f) * NC + c] = d[f];
-    }
-}
-
-// One axis of a leaf with the differences accumulated in one workspace
-// slice W (linear cell index): the x pass writes, the y pass adds, and the z
-// pass adds and finishes the cell, summing as (x + y) + z like the
-// three-slice path.  The caller separates the passes with a workgroup
-// barrier (a cell belongs to different lanes in different passes).
-__device__ __forceinline__ void col_axis_accumulate(int N, const StageArgs &a, const double *P,
-                                                    const ColLane &L, int leaf, double *W,
-                                                    double &smax) {
-    double dx, ox, oy, oz;
-    block_geometry(a, leaf, dx, ox, oy, oz);
-    double d[NF];
-    double sm = 0.0;
-    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
-    smax = L.live && sm > smax ? sm : smax;
-    if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
-        const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
-                    : (N == 1) ? (L.c2 * NX + L.cell) * NX + L.c1
-                               : (L.cell * NX + L.c2) * NX + L.c1;
-        if (N == 0) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) W[f * NC + c] = d[f];
-        } else if (N == 1) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) W[f * NC + c] = W[f * NC + c] + d[f];
-        } else {
-            double dsum[NF];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) dsum[f] = W[f * NC + c] + d[f];
-            finish_cell(a, leaf, c, dx, stage_dt(a), dsum);
-        }
     }
 }
 
@@ -786,27 +759,53 @@ __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, co
     }
 }
 
-// One leaf per workgroup, all three axes.
+// The columns [first, first + count) of a leaf as six-column tasks: a wave
+// takes task w (its index) first and then the next task from the counter in
+// LDS (which starts at the wave count), so the tasks spread evenly over the
+// SIMDs whatever the order the waves run in.  Columns of one axis write that
+// axis's slice of W only, so no barrier separates the axes.
+__device__ __forceinline__ void walk_columns(const StageArgs &a, const double *P, int leaf,
+                                             double *W, int first, int count, int *next_task,
+                                             int tid, double &smax) {
+    const int lane = tid & 63;
+    const int ntask = (count + COLS_PER_WAVE - 1) / COLS_PER_WAVE;
+    int task = tid >> 6;
+#pragma unroll 1
+    while (task < ntask) {
+        const ColLane L(lane, task, first, count);
+        col_axis_to_ws(L.axis, a, P, L, leaf, W, smax);
+        int t = 0;
+        if (lane == 0) t = atomicAdd(next_task, 1);
+        task = __builtin_amdgcn_readfirstlane(t);
+    }
+}
+
+// Maximum over the workgroup's waves of smax, left in red[0 .. NTC/64);
+// red may alias the input block (the barriers retire it first).
+__device__ __forceinline__ void block_max(double smax, double *red, int tid) {
+    const double wm = wave_max(smax);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = wm;
+    __syncthreads();
+}
+
+// One leaf per workgroup, all three axes, then the leaf is finished from
+// the three slices.
 __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
+    __shared__ int next_task;
     const int leaf = a.leaf0 + xcd_leaf(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
+    if (tid == 0) next_task = NTC / 64;
     gather_block<NTC>(P, a.Uin, a.gmap, leaf, a.ts, a.lg, a.prolong, a.n_prolong, tid);
     __syncthreads();
-    const ColLane L(tid);
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
     double smax = 0.0;
-#pragma unroll 1
-    for (int n = 0; n < 3; ++n) {
-        col_axis_accumulate(n, a, P, L, leaf, W, smax);
-        if (n < 2) __syncthreads();   // the slice's cells change owners between passes
-    }
-    const double wm = wave_max(smax);
-    __syncthreads();  // the input block is dead
-    double *red = P;
-    if (L.lane == 0) red[L.wave] = wm;
-    __syncthreads();
-    if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
+    walk_columns(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
+    __syncthreads();   // every slice of W is written
+    col_finish_leaf(a, leaf, W, tid, NTC);
+    block_max(smax, P, tid);
+    if (tid == 0 && a.amax) store_amax(a, leaf, P, NTC / 64);
 }
 
 // Persistent workgroups over a queue of (leaf, tile) items.  With one tile a
@@ -816,13 +815,15 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
 // workgroup to leave resets the queue for the next launch.
 __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) {
     __shared__ double P[NF * NP];
-    __shared__ int item_s, last_s;
+    __shared__ int item_s, last_s, next_task;
     const int tid = threadIdx.x;
-    const ColLane L(tid);
     const int T = a.tiles;
     const int items = a.nleaf * T;
     for (;;) {
-        if (tid == 0) item_s = atomicAdd(&a.queue[0], 1);
+        if (tid == 0) {
+            item_s = atomicAdd(&a.queue[0], 1);
+            next_task = NTC / 64;
+        }
         __syncthreads();
         const int item = item_s;
         if (item >= items) break;
@@ -833,25 +834,17 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
         if (T == 1) {
-#pragma unroll 1
-            for (int n = 0; n < 3; ++n) {
-                col_axis_accumulate(n, a, P, L, leaf, W, smax);
-                if (n < 2) __syncthreads();
-            }
+            walk_columns(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
+            __syncthreads();   // every slice of W is written
+            col_finish_leaf(a, leaf, W, tid, NTC);
+            block_max(smax, P, tid);
+            if (tid == 0 && a.amax) store_amax(a, leaf, P, NTC / 64);
         } else {
-            col_axis_to_ws(tile, a, P, L, leaf, W, smax);
-        }
-        const double wm = wave_max(smax);
-        __syncthreads();
-        double *red = P;
-        if (L.lane == 0) red[L.wave] = wm;
-        __syncthreads();
-        if (T == 1) {
-            if (tid == 0 && a.amax) store_amax(a, leaf, red, NTC / 64);
-        } else {
+            walk_columns(a, P, leaf, W, tile * NX * NX, NX * NX, &next_task, tid, smax);
+            block_max(smax, P, tid);
             if (tid == 0) {
-                double m = red[0];
-                for (int w = 1; w < NTC / 64; ++w) m = red[w] > m ? red[w] : m;
+                double m = P[0];
+                for (int w = 1; w < NTC / 64; ++w) m = P[w] > m ? P[w] : m;
                 a.tile_amax[(size_t)leaf * 3 + tile] = m;
                 __threadfence();   // publish W and the tile maximum device-wide
                 last_s = atomicAdd(&a.leaf_done[leaf], 1) == T - 1;
@@ -873,7 +866,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
                 }
             }
         }
-        __syncthreads();   // LDS and item_s are reused by the next item
+        __syncthreads();   // LDS, item_s and next_task are reused by the next item
     }
     if (tid == 0) {
         __threadfence();
