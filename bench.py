@@ -42,6 +42,19 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+def autotuned(hy, g):
+    """Autotune the grid's schedules: the per-size table, and the single
+    schedule the tuner keeps for whole stages of the grid's partition
+    ("table" when it keeps the table)."""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        table = hy.autotune(g, path)
+        with open(path) as f:
+            conc = json.load(f).get("concurrent", -1)
+    return table, {1: "face", 2: "column", 3: "persistent", 4: "tiled"}.get(conc, "table")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,7 +190,7 @@ def binary_leg(torch, args, params):
             if on:
                 hy.mlp_load(params)
             torch.cuda.synchronize()
-            hy.autotune(g)
+            _, conc = autotuned(hy, g)
             dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
             hy.dt(g, w.cfl, dt_dev)
             hy.graph_capture(g, w.cfl, dt_dev, nsteps)
@@ -193,7 +206,7 @@ def binary_leg(torch, args, params):
             results[name] = g.U.cpu().numpy()
             out[name] = {"value": w.cells * 2 * nsteps / el, "unit": "cell-updates/s",
                          "ms_per_step": el / nsteps * 1e3, "launches_per_stage": len(off) - 1,
-                         "dt_after": float(dt_dev.item())}
+                         "dt_after": float(dt_dev.item()), "autotune_concurrent": conc}
             if on:
                 cells, fb = hy.mlp_stats()
                 out[name]["fallback_fraction"] = fb / max(cells, 1)
@@ -225,7 +238,7 @@ def batched_legs(torch, args, params):
             g = hy.grid(w.tree, U0.clone(), w.omega, w.gamma, launch_off=off)
             if on:
                 hy.mlp_load(params)
-            t_ = hy.autotune(g)
+            t_, conc = autotuned(hy, g)
             table = t_ if table is None else table
             if not on:   # both paths step with the plain path's CFL time step
                 dt = float(w.cfl * np.min(w.tree.dx / hy.signal_speed(g).cpu().numpy()))
@@ -243,7 +256,7 @@ def batched_legs(torch, args, params):
             cells, fb = hy.mlp_stats() if on else (0, 0)
             results[name] = g.U.cpu().numpy()
             out[name] = {"value": w.cells * 2 / med, "unit": "cell-updates/s", "ms_per_step": med * 1e3,
-                         "launches_per_stage": len(off) - 1}
+                         "launches_per_stage": len(off) - 1, "autotune_concurrent": conc}
             if on:
                 out[name]["fallback_fraction"] = fb / max(cells, 1)
         finally:
