@@ -44,13 +44,15 @@ __device__ __forceinline__ int pidx(int i, int j, int k) {
 // kernel and spilled (a scratch write stream of ~170 B per lane per launch).
 __device__ __attribute__((noinline)) double pow_cold(double x, double y) { return pow(x, y); }
 
-// tau^gamma of the dual-energy switch, out of line like pow_cold.  For
-// gamma = 5/3 (the double nearest it), tau^(5/3) = tau^2 tau^(-1/3) with the
-// cube root by two Newton steps, y <- y (4 - a y^3) / 3, from a
-// single-precision estimate of a^(-1/3), where tau = m 2^e, e = 3k + r and
-// a = m 2^r in [0.5, 4): within a few ulp of the exact power, several times
-// cheaper than pow; other exponents and tau outside [2^-330, 2^330] take pow.
-__device__ __attribute__((noinline)) double pow_tau(double x, double g) {
+// tau^gamma of the dual-energy switch.  For gamma = 5/3 (the double nearest
+// it), tau^(5/3) = tau^2 tau^(-1/3) with the cube root by two Newton steps,
+// y <- y (4 - a y^3) / 3, from a single-precision estimate of a^(-1/3), where
+// tau = m 2^e, e = 3k + r and a = m 2^r in [0.5, 4): within a few ulp of the
+// exact power, several times cheaper than pow; other exponents and tau
+// outside [2^-330, 2^330] take pow_cold.  Inlined: a wave whose lanes hit the
+// switch (leaves behind a strong shock) runs it at every face point, and the
+// call's overhead made those leaves, which set the launch's length, 9% slower.
+__device__ __forceinline__ double pow_tau(double x, double g) {
     if (g == 5.0 / 3.0 && x >= 0x1p-330 && x <= 0x1p+330) {
         int e;
         const double m = frexp(x, &e);
@@ -61,7 +63,7 @@ __device__ __attribute__((noinline)) double pow_tau(double x, double g) {
         y = y * (4.0 - a * y * y * y) * (1.0 / 3.0);
         return x * x * ldexp(y, -k);
     }
-    return pow(x, g);
+    return pow_cold(x, g);
 }
 
 // Monotonised-central slope of the middle value (zero at an extremum),
@@ -833,14 +835,15 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         __syncthreads();
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
+        // one tile: all 192 columns; three: the 64 columns of axis `tile`
+        walk_columns(a, P, leaf, W, T == 1 ? 0 : tile * NX * NX, T == 1 ? 3 * NX * NX : NX * NX,
+                     &next_task, tid, smax);
         if (T == 1) {
-            walk_columns(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
             __syncthreads();   // every slice of W is written
             col_finish_leaf(a, leaf, W, tid, NTC);
             block_max(smax, P, tid);
             if (tid == 0 && a.amax) store_amax(a, leaf, P, NTC / 64);
         } else {
-            walk_columns(a, P, leaf, W, tile * NX * NX, NX * NX, &next_task, tid, smax);
             block_max(smax, P, tid);
             if (tid == 0) {
                 double m = P[0];
