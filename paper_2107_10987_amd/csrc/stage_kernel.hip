@@ -67,11 +67,12 @@ __device__ __forceinline__ double pow_tau(double x, double g) {
 }
 
 // Monotonised-central slope of the middle value (zero at an extremum),
-// computed as (sign dl + sign dr) min(|q+ - q-| / 4, |dl|, |dr|): scaling by
-// 2 commutes exactly with min, so 2 min(...) is min(|q+ - q-| / 2, 2 |dl|,
-// 2 |dr|) bit for bit, and the sign sum is +-2 where dl and dr agree and 0 at
-// an extremum (a zero difference makes the min zero), so neither the two
-// doublings nor a select are needed.
+// computed as m sign dl + m sign dr with m = min(|q+ - q-| / 4, |dl|, |dr|):
+// scaling by 2 commutes exactly with min, so 2 m is min(|q+ - q-| / 2,
+// 2 |dl|, 2 |dr|) bit for bit; the sum is 2m (exact) with the common sign
+// where dl and dr agree, +0 where they differ, and a zero of the right sign
+// where a difference is zero (m is then zero), so neither the two doublings
+// nor a select nor a multiply are needed.
 __device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     const double dl = q0 - qm;
     const double dr = qp - q0;
@@ -79,7 +80,7 @@ __device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
     // all three operands are finite and non-negative, so fmin (one FP64
     // instruction) selects exactly what the comparisons would
     const double m = fmin(fmin(fabs(d), fabs(dl)), fabs(dr));
-    return (copysign(1.0, dl) + copysign(1.0, dr)) * m;
+    return copysign(m, dl) + copysign(m, dr);
 }
 
 // PPM on five values q0..q4 along a line, with the CW84 limiter: left (toward
