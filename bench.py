@@ -340,7 +340,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the hydro path is not sharded across GPUs in this build)", file=sys.stderr)
+              "(the hydro path runs on one GPU; it is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 

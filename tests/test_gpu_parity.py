@@ -2,7 +2,7 @@
 identical seeded inputs.
 
 Tolerance (FP64): per field f, max |gpu - oracle| / max(max |oracle_f|, 1e-300)
-<= 1e-12, the bound the build is held to; both sides evaluate the same
+<= 1e-12, the parity bound for FP64 results; both sides evaluate the same
 expressions with contraction off, so most results agree to the last bit."""
 import numpy as np
 import pytest
