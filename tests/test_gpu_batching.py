@@ -51,6 +51,46 @@ def test_device_dt_step_matches_host_dt(torch):
         hy.close()
 
 
+@pytest.mark.parametrize("rk", [2, 3])
+def test_device_dt_one_and_two_launches(torch, rk):
+    # the same grid as one column launch per stage and as two concurrent
+    # launches gives the same device time steps and states bit for bit,
+    # eagerly and replayed from a graph
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: device dt, one vs two launches per stage, sedov-32^3, RK{rk}", flush=True)
+    w = sedov_uniform(4)
+    one = Hydro(max_leaves=w.n, schedule="column", rk_order=rk)
+    two = Hydro(max_leaves=w.n, schedule="column", rk_order=rk)
+    gr = Hydro(max_leaves=w.n, schedule="column", rk_order=rk)
+    try:
+        s = torch.cuda.Stream()
+        U0 = torch.tensor(w.U, device="cuda")
+        ga = one.grid(w.tree, U0.clone(), w.omega, w.gamma)
+        gb = two.grid(w.tree, U0.clone(), w.omega, w.gamma,
+                      launch_off=np.array([0, w.n // 2, w.n], np.int32))
+        gg = gr.grid(w.tree, U0.clone(), w.omega, w.gamma, stream=s)
+        da, db, dg = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(3))
+        torch.cuda.synchronize()
+        one.dt(ga, w.cfl, da)
+        two.dt(gb, w.cfl, db)
+        gr.dt(gg, w.cfl, dg)
+        torch.cuda.synchronize()
+        gr.graph_capture(gg, w.cfl, dg, 3)
+        torch.cuda.synchronize()
+        for replay in range(2):
+            for _ in range(3):
+                one.step_dev(ga, w.cfl, da)
+                two.step_dev(gb, w.cfl, db)
+            gr.graph_launch(s)
+            torch.cuda.synchronize()
+            assert da.item() == db.item() == dg.item(), (replay, da.item(), db.item(), dg.item())
+            assert torch.equal(ga.U, gb.U) and torch.equal(ga.U, gg.U), replay
+    finally:
+        one.close()
+        two.close()
+        gr.close()
+
+
 def test_timing_counts_the_stage_launches_of_steps(torch):
     from paper_2107_10987_amd.hydro import Hydro
     print("case: stage timing, 3 device-dt steps of sedov-32^3 (RK2 and RK3)", flush=True)
