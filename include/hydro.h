@@ -223,8 +223,9 @@ int hydro_graph_launch(hydro_t *h, void *stream);
  * NULL) receives it, and cache_path (may be NULL) a JSON copy.  When g has
  * several launches per stage (which run concurrently), whole stages of that
  * partition are also timed with the table and with each schedule for every
- * launch, and a single schedule that is clearly faster is used for stages of
- * several launches (kept in the JSON copy as "concurrent").  Uses only the
+ * launch (two interleaved rounds, each candidate's faster one counting), and
+ * the fastest of these is used for stages of several launches (kept in the
+ * JSON copy as "concurrent": -1 for the table).  Uses only the
  * handle's workspace; g->U is read, not written.  Synchronous. */
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
 

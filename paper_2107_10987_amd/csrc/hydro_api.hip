@@ -864,35 +864,38 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
     // the grid's own partition: its launches run concurrently, where a small
     // launch's latency hides behind the large ones and the chip's total work
     // decides; time whole stages with the per-size table and with each
-    // schedule for every launch, keep the fastest
+    // schedule for every launch, in two interleaved rounds (each candidate
+    // keeps its faster round, so drift of the chip's clock between
+    // candidates does not decide), and keep the fastest
     h->multi_sched = -1;
     h->table_loaded = true;
     if (rc == HYDRO_OK && g->n_launch > 1) {
         hydro_grid part = *g;
         part.n_reflux = 0;
         h->p.schedule = HYDRO_SCHED_AUTO;
-        float best_ms = 1e30f;
-        int best = -1;
-        const int cand[4] = {-1, HYDRO_SCHED_COLUMN, HYDRO_SCHED_PERSISTENT, HYDRO_SCHED_TILED};
-        for (int ci = 0; ci < 4 && rc == HYDRO_OK; ++ci) {
-            h->multi_sched = cand[ci];
-            rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);   // warm
-            if (rc) break;
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < 3 && rc == HYDRO_OK; ++r)
-                rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);
-            (void)hipEventRecord(e1, s);
-            float ms = 0.f;
-            hipError_t e = hipEventSynchronize(e1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { rc = hip_fail(h, e, "autotune timing"); break; }
-            // the table is kept unless a single schedule is clearly faster
-            if (ci == 0 || ms < 0.98f * best_ms) {
-                best_ms = ms;
-                best = cand[ci];
+        constexpr int NCAND = 4, ROUNDS = 2, REPS = 3;
+        const int cand[NCAND] = {-1, HYDRO_SCHED_COLUMN, HYDRO_SCHED_PERSISTENT, HYDRO_SCHED_TILED};
+        float cand_ms[NCAND] = {1e30f, 1e30f, 1e30f, 1e30f};
+        for (int round = 0; round < ROUNDS && rc == HYDRO_OK; ++round) {
+            for (int ci = 0; ci < NCAND && rc == HYDRO_OK; ++ci) {
+                h->multi_sched = cand[ci];
+                rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);   // warm
+                if (rc) break;
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < REPS && rc == HYDRO_OK; ++r)
+                    rc = run_stage(h, &part, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);
+                (void)hipEventRecord(e1, s);
+                float ms = 0.f;
+                hipError_t e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { rc = hip_fail(h, e, "autotune timing"); break; }
+                if (ms < cand_ms[ci]) cand_ms[ci] = ms;
             }
         }
-        h->multi_sched = best;
+        int best = 0;
+        for (int ci = 1; ci < NCAND; ++ci)
+            if (cand_ms[ci] < cand_ms[best]) best = ci;
+        h->multi_sched = cand[best];
     }
     h->p.schedule = saved_sched;
     (void)hipEventDestroy(e0);
