@@ -118,10 +118,13 @@ typedef struct hydro_tree {
 /* Allocate every workspace the step needs (state copy for the first stage,
  * per-tile flux differences of the column-walk schedule (86,016 B per 8^3
  * tile), per-tile signal speeds, error flags) for up to p->max_leaves leaves on
- * p->device.  No later call allocates device memory.  *out is NULL on error. */
+ * p->device.  No later call allocates device memory.  *out is NULL on error.
+ * Source: section IV-C1 (device buffers and streams are created up front and
+ * reused, because allocation synchronises the whole GPU). */
 int hydro_create(const hydro_params *p, hydro_t **out);
 
-/* Free the workspace; idempotent on NULL. */
+/* Free the workspace; idempotent on NULL.  Source: section IV-C1 (the
+ * handle owns every buffer it pre-allocated). */
 int hydro_destroy(hydro_t *h);
 
 /* Build the ghost map of a tree on the host into map[t->n][T][2232] (caller-owned
@@ -129,7 +132,10 @@ int hydro_destroy(hydro_t *h);
  * the leaf's level; a same-level cell; the covering cell of a coarser leaf
  * (injection); or the mean of the 2x2x2 cells of a leaf one level finer.
  * Returns HYDRO_EINVAL if the tree is not 2:1 balanced or a leaf is outside
- * the box.  Synchronous; needs no handle and no GPU. */
+ * the box.  Synchronous; needs no handle and no GPU.  Source: section IV-B
+ * (leaf sub-grids of an AMR octree) and section IV-C1 (each kernel reads
+ * its sub-grid's cells and the cells of its ghost layer); the fill rules
+ * themselves are not given in the paper. */
 int hydro_ghost_map(const hydro_tree *t, int32_t *map);
 
 /* hydro_ghost_map with linear-limited prolongation: a ghost cell inside a
@@ -167,7 +173,9 @@ int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, in
  *     the two other axes (in increasing axis order) are o1, o2; -1 for faces
  *     without finer blocks.
  * Returns HYDRO_EINVAL if the tree is not 2:1 balanced across a face or a
- * leaf is outside the box.  Synchronous; needs no handle and no GPU. */
+ * leaf is outside the box.  Synchronous; needs no handle and no GPU.
+ * Source: section IV-B (AMR octree); the matching itself is not in the
+ * paper. */
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries);
 
 /* One full SSP Runge-Kutta step of all leaves, in place on g->U (Shu-Osher
@@ -180,7 +188,11 @@ int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries,
  * writes each leaf's maximum signal speed over both stages and reports
  * HYDRO_ENONPHYS if a stage produced rho <= 0 or a non-finite value.  Otherwise
  * it returns without waiting and the speeds stay in the handle
- * (hydro_amax_device). */
+ * (hydro_amax_device).  Source: section IV-B (reconstruction at the 26
+ * points, central-upwind fluxes, Newtonian face quadrature, rotating frame,
+ * entropy tracer); section V-A2 (three Runge-Kutta stages per step); every
+ * leaf of the call in one launch per stage is the aggregation of section
+ * IV-C3. */
 int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out);
 
 /* One stage with explicit buffers (device, [n][7][512] each; Uin provides the
@@ -188,32 +200,44 @@ int hydro_step(hydro_t *h, const hydro_grid *g, double dt, double *amax_out);
  * handle's order: Uout = a Un + b (Uin + dt L(Uin)) with the coefficients
  * above, and the tracer resync after the last stage.  Uout may alias Un, not
  * Uin.  amax (device [n], may be NULL) receives each leaf's maximum signal
- * speed.  g->U is not used. */
+ * speed.  g->U is not used.  Source: section IV-B (one evaluation of the
+ * scheme), section V-A2 (a Runge-Kutta stage). */
 int hydro_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const double *Uin,
                 const double *Un, double *Uout, double *amax);
 
-/* Maximum signal speed of each leaf for the state g->U: amax (device [n]). */
+/* Maximum signal speed of each leaf for the state g->U: amax (device [n]).
+ * Source: section IV-B (the central-upwind scheme's local speeds at the
+ * quadrature points). */
 int hydro_signal_speed(hydro_t *h, const hydro_grid *g, double *amax);
 
 /* Reconstructed values of every interior cell at its 26 points:
  * out (device [n][7][512][26]); point d = (dx,dy,dz) is numbered
- * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre.  8^3 leaves only. */
+ * 9(dz+1) + 3(dy+1) + (dx+1), minus one past the centre.  8^3 leaves only.
+ * Source: section IV-B (PPM along the 13 lines through the cell centre,
+ * left and right values at the 26 quadrature points). */
 int hydro_reconstruct(hydro_t *h, const hydro_grid *g, double *out);
 
 /* One SSP-RK2 step driven on the device: both stages read dt from dt_dev
  * (device, one double); afterwards dt_dev holds the next step,
  * cfl * min over leaves of dx / a_max over both stages.  Never synchronises
- * and never allocates, so it can be captured into a HIP graph. */
+ * and never allocates, so it can be captured into a HIP graph.  Source:
+ * section IV-B (the scheme), section V-A2 (Runge-Kutta stages); the time
+ * step from the signal speeds is not given in the paper (CFL 0.4 here);
+ * running without host round trips answers the launch overheads of
+ * section IV-C3. */
 int hydro_step_dev(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev);
 
 /* dt_dev = cfl * min over leaves of dx / a_max(g->U): the first step of a run
- * (signal-speed pre-pass; asynchronous). */
+ * (signal-speed pre-pass; asynchronous).  Source: section IV-B (local
+ * speeds of the central-upwind scheme). */
 int hydro_dt(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev);
 
 /* Capture nsteps hydro_step_dev calls on g->stream (must not be NULL) into
  * a HIP graph held by the handle, replacing any earlier one; the grid's
  * buffers and launch partition are baked in.  hydro_graph_launch replays it
- * on `stream`. */
+ * on `stream`.  Source: section IV-C3 (many small kernels starve the GPU;
+ * aggregating them is proposed there and in section VII-A as future work);
+ * graphs are this library's answer, not the paper's. */
 int hydro_graph_capture(hydro_t *h, const hydro_grid *g, double cfl, double *dt_dev, int nsteps);
 int hydro_graph_launch(hydro_t *h, void *stream);
 
@@ -226,7 +250,9 @@ int hydro_graph_launch(hydro_t *h, void *stream);
  * launch (two interleaved rounds, each candidate's faster one counting), and
  * the fastest of these is used for stages of several launches (kept in the
  * JSON copy as "concurrent": -1 for the table).  Uses only the
- * handle's workspace; g->U is read, not written.  Synchronous. */
+ * handle's workspace; g->U is read, not written.  Synchronous.  Source:
+ * section IV-C3 (the launch configuration and sub-grids per kernel decide
+ * GPU utilisation) and section VII-A (tuning the kernels is future work). */
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
 
 /* ---- learned reconstruction ----------------------------------------------
@@ -240,7 +266,8 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
  * cell any of whose fields fails takes plain PPM.  Fluxes, update and
  * conservation stay FP64.
  * Parameters: float32 vector of 8090 values, W1[64][34], b1[64], W2[64][64],
- * b2[64], W3[26][64], b3[26].  Not a method of the paper: an extension. */
+ * b2[64], W3[26][64], b3[26].  Not a method of the paper: an extension; the
+ * calls below cite no section. */
 
 /* Set the network's parameters (host [8090]); resets the Adam state.
  * Non-finite parameters are accepted: every row they touch fails the check
@@ -270,12 +297,14 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
 int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback);
 
 /* Device pointer to the maximum signal speeds of the last step, one per 8^3
- * tile ([n] for 8^3 leaves, [n][8] for 16^3 leaves). */
+ * tile ([n] for 8^3 leaves, [n][8] for 16^3 leaves).  Source: section IV-B
+ * (local speeds). */
 const double *hydro_amax_device(const hydro_t *h);
 
 /* Synchronise the handle's last stream and report HYDRO_ENONPHYS if any
  * stage since the previous check produced rho <= 0 or a non-finite value;
- * clears the flag. */
+ * clears the flag.  The paper names no floors; a non-physical state is an
+ * error here. */
 int hydro_check(hydro_t *h, void *stream);
 
 /* Stage-kernel timing.  enable = 1 starts recording a HIP event pair around
@@ -284,9 +313,12 @@ int hydro_check(hydro_t *h, void *stream);
  * hydro_dt is not recorded); enable = 0 stops.  If total_ms / launches are non-NULL the call
  * first waits for the recorded events and reports the summed kernel time (ms)
  * and the number of launches timed since the previous report, then clears
- * them.  Event objects are created on the first enable. */
+ * them.  Event objects are created on the first enable.  Measurement
+ * support (section V-A1 reports per-kernel times); not part of the method. */
 int hydro_timing(hydro_t *h, int enable, double *total_ms, int64_t *launches);
 
+/* Text of a return code, and of the last error of a handle (NULL: of the
+ * last hydro_create).  Library support; not part of the method. */
 const char *hydro_strerror(int code);
 const char *hydro_last_error(const hydro_t *h);
 

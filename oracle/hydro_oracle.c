@@ -150,7 +150,10 @@ double oracle_point_flux(int n, const double UL[7], const double UR[7], const do
     double FL[7], FR[7];
     double sl = side_flux(n, UL, xq, ph, FL);
     double sr = side_flux(n, UR, xq, ph, FR);
-    double a = sl > sr ? sl : sr;
+    /* a side without a real sound speed (rho <= 0, or a negative or non-finite
+     * pressure) has no signal speed: the maximum is then undefined and the
+     * point flux is NaN, so the stage reports a non-physical result */
+    double a = (isnan(sl) || isnan(sr)) ? (double)NAN : (sl > sr ? sl : sr);
     for (int f = 0; f < NFLD; ++f)
         F[f] = 0.5 * (FL[f] + FR[f]) - 0.5 * a * (UR[f] - UL[f]);
     return a;

@@ -41,6 +41,8 @@ inline cd fabs(cd a) { return cd(std::fabs(a.v)); }
 inline cd copysign(cd a, cd b) { return cd(std::copysign(a.v, b.v)); }
 inline cd sqrt(cd a) { ++g_flop; return cd(std::sqrt(a.v)); }
 inline cd pow(cd a, cd b) { ++g_flop; return cd(std::pow(a.v, b.v)); }
+// a classification, not arithmetic: not counted
+inline bool isnan(cd a) { return std::isnan(a.v); }
 
 #define double cd
 #include "hydro_oracle.c"

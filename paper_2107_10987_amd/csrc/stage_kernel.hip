@@ -268,7 +268,9 @@ __device__ __forceinline__ void face_flux(const double *P, int r, double dx, con
             const double yq = xB[1] + 0.5 * (double)dB[1] * dx;
             const double sl = side_flux<N>(UL, xq, yq, ph, FL);
             const double sr = side_flux<N>(UR, xq, yq, ph, FR);
-            const double s = sl > sr ? sl : sr;
+            // a NaN speed (a side without a real sound speed) makes the
+            // point flux NaN, so the stage reports the non-physical state
+            const double s = fmax(sl, sr) + 0.0 * (sl + sr);
             smax = s > smax ? s : smax;
             const double w = centre_only ? 1.0 : ((a == 0) ? wc[b + 1] : wts[b + 1]);
 #pragma unroll
@@ -619,7 +621,10 @@ __device__ __forceinline__ double point_flux_acc(int n, const double UL[NF], con
     double FL[NF], FR[NF];
     const double sl = side_flux_rt(n, UL, xq, yq, ph, FL);
     const double sr = side_flux_rt(n, UR, xq, yq, ph, FR);
-    const double s = fmax(sl, sr);
+    // fmax drops a NaN operand; adding 0 (sl + sr) restores it, so a side
+    // without a real sound speed (rho <= 0, p < 0) makes the point flux NaN
+    // and the stage reports the non-physical state
+    const double s = fmax(sl, sr) + 0.0 * (sl + sr);
     {
 #pragma clang fp contract(fast)
 #pragma unroll

@@ -46,11 +46,7 @@ def _state(tree, seed=5):
     return np.ascontiguousarray(conserved_from_primitive(rho, vx, vy, vz, p, spc, G))
 
 
-def field_err(g, o):
-    g = np.asarray(g).reshape(g.shape[0], 7, -1)
-    o = np.asarray(o).reshape(o.shape[0], 7, -1)
-    return np.array([np.abs(g[:, f] - o[:, f]).max() / max(np.abs(o[:, f]).max(), 1e-300)
-                     for f in range(7)])
+from parity import check, field_err  # noqa: E402
 
 
 @pytest.mark.parametrize("schedule,reflux", [("column", False), ("face", False), ("persistent", True),
@@ -73,10 +69,9 @@ def test_prolongation_steps_match_oracle(torch, schedule, reflux):
         Uo = U
         for s in range(3):
             am = hy.step(g, dt)
+            Uprev = Uo
             Uo, amo = o.step(dt, Uo)
-            err = field_err(g.U.cpu().numpy(), Uo)
-            print(f"step {s} err", err, flush=True)
-            assert np.all(err <= TOL), err
+            check(g.U.cpu().numpy(), Uo, o, Uprev, size=7, label=f"prolongation step {s}")
             dt = float(0.4 * np.min(t.dx / amo))
     finally:
         hy.close()
@@ -141,9 +136,7 @@ def test_prolongation_polytrope_uneven_launches(torch):
         dt = float(w.cfl * np.min(w.tree.dx / o.signal_speed(w.U)))
         hy.step(g, dt)
         Uo, _ = o.step(dt, w.U)
-        err = field_err(g.U.cpu().numpy(), Uo)
-        print("polytrope prolongation err", err, flush=True)
-        assert np.all(err <= TOL), err
+        check(g.U.cpu().numpy(), Uo, o, w.U, size=7, label="polytrope prolongation")
     finally:
         hy.close()
 

@@ -49,11 +49,7 @@ def _state(tree, seed=5):
     return np.ascontiguousarray(conserved_from_primitive(rho, vx, vy, vz, p, spc, G))
 
 
-def field_err(g, o):
-    g = np.asarray(g).reshape(g.shape[0], 7, -1)
-    o = np.asarray(o).reshape(o.shape[0], 7, -1)
-    return np.array([np.abs(g[:, f] - o[:, f]).max() / max(np.abs(o[:, f]).max(), 1e-300)
-                     for f in range(7)])
+from parity import check, field_err  # noqa: E402
 
 
 @pytest.mark.parametrize("schedule", ["column", "face", "persistent", "tiled"])
@@ -74,18 +70,15 @@ def test_reflux_stages_and_steps_match_oracle(torch, schedule):
         U1 = torch.empty_like(g.U)
         am = torch.zeros(t.n, dtype=torch.float64, device="cuda")
         hy.stage(g, 1, dt, g.U, None, U1, am)
-        err = field_err(U1.cpu().numpy(), U1o)
-        print("stage 1 err", err, flush=True)
-        assert np.all(err <= TOL), err
+        check(U1.cpu().numpy(), U1o, o, U, label="reflux stage 1")
         assert np.abs(am.cpu().numpy() - a1o).max() <= TOL * a1o.max()
         # three whole steps
         Uo = U
         for s in range(3):
             amax = hy.step(g, dt)
+            Uprev = Uo
             Uo, amo = o.step(dt, Uo)
-            err = field_err(g.U.cpu().numpy(), Uo)
-            print(f"step {s} err", err, flush=True)
-            assert np.all(err <= TOL), err
+            check(g.U.cpu().numpy(), Uo, o, Uprev, size=7, label=f"reflux step {s}")
             dt = float(0.4 * np.min(t.dx / amo))
     finally:
         hy.close()
@@ -135,9 +128,7 @@ def test_reflux_polytrope_uneven_launches(torch):
         dt = float(w.cfl * np.min(w.tree.dx / o.signal_speed(w.U)))
         hy.step(g, dt)
         Uo, _ = o.step(dt, w.U)
-        err = field_err(g.U.cpu().numpy(), Uo)
-        print("polytrope reflux err", err, flush=True)
-        assert np.all(err <= TOL), err
+        check(g.U.cpu().numpy(), Uo, o, w.U, size=7, label="polytrope reflux")
     finally:
         hy.close()
 

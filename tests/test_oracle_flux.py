@@ -111,3 +111,16 @@ def test_simpson_face_quadrature(oracle_mod):
     assert np.allclose(got, expect[None, :, None], rtol=1e-14, atol=0)
     # the midpoint rule would give u0*Q(j); make sure the test can tell
     assert np.max(np.abs(u0 * Q(jj) - expect)) > 1e-4
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_state_without_sound_speed_gives_nan_flux(oracle_mod, side):
+    # a point state of negative density has no real sound speed, so the
+    # maximum signal speed is undefined on either side; the flux is NaN and
+    # the stage's result is reported as non-physical
+    good = state(1.0, [0.2, 0.0, 0.0], 1.0)
+    bad = good.copy()
+    bad[0] = -0.5
+    UL, UR = (bad, good) if side == "left" else (good, bad)
+    F, a = oracle_mod.point_flux(0, UL, UR, [0, 0, 0])
+    assert np.isnan(a) and np.isnan(F).all()
