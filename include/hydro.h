@@ -255,6 +255,28 @@ int hydro_graph_launch(hydro_t *h, void *stream);
  * GPU utilisation) and section VII-A (tuning the kernels is future work). */
 int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int32_t *table);
 
+/* ---- allocation-free step ------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one SSP-RK2
+ * step of hydro_step (plain PPM, the column-walk kernel, one launch per
+ * stage), without a handle.  Its workspace -- the stage-1 state, the column
+ * walk's flux differences, per-leaf signal speeds when amax is NULL and the
+ * status word, 7.3 MB for HYDRO_NOALLOC_MAX_LEAVES leaves -- is one fixed
+ * device array of the library that every GPU it runs on holds until the
+ * process ends; the call allocates nothing.  It runs on the calling thread's
+ * current device, in place on g->U (8^3 leaves; g->n <= HYDRO_NOALLOC_MAX_LEAVES,
+ * else HYDRO_EINVAL; launch partitions are ignored; no flux correction;
+ * linear-prolongation tables are used).  amax (device [g->n], may be NULL)
+ * receives each leaf's maximum signal speed over both stages.  The first call
+ * on a device looks up the array and uploads the ghost tables, and must not
+ * be captured (HYDRO_EINVAL if it is).  sync = 0: asynchronous on g->stream,
+ * graph-capturable; sync = 1: waits for the stream and reports HYDRO_ENONPHYS
+ * if a stage produced rho <= 0 or a non-finite value.  Errors set
+ * hydro_last_error(NULL).  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams, other threads) race. */
+#define HYDRO_NOALLOC_MAX_LEAVES 64
+int hydro_step_noalloc(const hydro_grid *g, double dt, double eta1, double eta2, double *amax, int sync);
+
 /* ---- learned reconstruction ----------------------------------------------
  * A 34-64-64-26 network (tanh-GELU) maps the normalised 3x3x3 neighbourhood of
  * a cell, x_k = (q_nb - q_c)/sigma with sigma = max |q_nb - q_c|, plus a

@@ -602,6 +602,11 @@ int build_ghost_map(const hydro_tree *t, int32_t *map, int32_t *table, int32_t c
 
 }  // namespace
 
+// Set-up and error text shared with the allocation-free entry point
+// (hydro_noalloc.hip), which has no handle.
+hipError_t hydro_internal_ghost_table(int dev) { return ensure_ghost_table(dev); }
+void hydro_internal_set_error(const char *msg) { g_create_err = msg; }
+
 extern "C" {
 
 int hydro_create(const hydro_params *p, hydro_t **out) {

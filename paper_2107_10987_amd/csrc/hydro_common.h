@@ -193,6 +193,10 @@ __device__ __forceinline__ int xcd_leaf(int b, int n) {
 
 // Launchers implemented in the kernel translation unit.
 hipError_t hydro_upload_ghost_table(const uint16_t *table);
+// Host helpers of the API translation unit: one-time upload of the ghost-slot
+// tables to a device, and the thread's handle-less error text.
+hipError_t hydro_internal_ghost_table(int dev);
+void hydro_internal_set_error(const char *msg);
 hipError_t hydro_launch_stage(const hydro::StageArgs &a, hipStream_t s);
 hipError_t hydro_launch_reflux(const hydro::RefluxArgs &r, int n_entries, hipStream_t s);
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, int ts, double cfl,

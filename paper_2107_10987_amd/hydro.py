@@ -25,7 +25,9 @@ EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_ghost_map_
            "hydro_graph_capture", "hydro_graph_launch", "hydro_autotune", "hydro_mlp_load",
            "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
            "hydro_mlp_pairs", "hydro_mlp_stats", "hydro_amax_device",
-           "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error")
+           "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error",
+           "hydro_step_noalloc")
+NOALLOC_MAX_LEAVES = 64
 SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
 NBUCKET = 16
 
@@ -101,6 +103,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_strerror.restype = C.c_char_p
     L.hydro_last_error.argtypes = [vp]
     L.hydro_last_error.restype = C.c_char_p
+    L.hydro_step_noalloc.argtypes = [C.POINTER(Grid), C.c_double, C.c_double, C.c_double, vp, C.c_int]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.hydro_amax_device.restype = vp
@@ -174,6 +177,19 @@ def _ptr(t) -> int:
 
 def _sptr(stream):
     return None if stream is None else (int(stream.cuda_stream) or None)
+
+
+def step_noalloc(g: "DeviceGrid", dt: float, eta1: float = 1e-3, eta2: float = 1e-1, amax=None,
+                 sync: bool = True):
+    """One SSP-RK2 step of g (8^3 leaves, at most NOALLOC_MAX_LEAVES) through
+    the allocation-free entry point: no handle, the library's fixed device
+    scratch array; amax (device float64 [n] or None) receives the per-leaf
+    signal speeds."""
+    L = load()
+    rc = L.hydro_step_noalloc(C.byref(g.c), float(dt), float(eta1), float(eta2), _ptr(amax) or None,
+                              int(bool(sync)))
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
 
 
 class Hydro:
