@@ -314,6 +314,19 @@ int hydro_mlp_train_step(hydro_t *h, const float *X, const float *T, int B, doub
  * plain PPM point values in the same normalisation T (device [n*3584][26]),
  * valid (device [n*3584], 0 where the neighbourhood is flat).  8^3 leaves only. */
 int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t *valid);
+/* The learned reconstruction's pre-pass of a stage alone, for the state g->U
+ * (test and inspection support).  For every 8^3 block b (T per leaf) and every
+ * cell slot s its fluxes need -- the 512 interior cells by index, then the 64
+ * cells of each face-adjacent ghost slab x-, x+, y-, y+, z-, z+ by their two
+ * in-block coordinates in axis order (slot 512 + 64 slab + u + 8 v) --
+ * val (device [n T][7][26][896], [block][field][point][slot]; points numbered
+ * as in hydro_reconstruct) receives the limited FP64 point values, and ok
+ * (device uint8 [n T][896]) 1 where the cell passes the FP64 check in all
+ * seven fields, 0 where the stage takes plain PPM for it.  y (device float
+ * [n T][7][896][26], may be NULL) receives the network's outputs of every row
+ * whose neighbourhood is not flat (other rows may be left untouched).
+ * Counts toward hydro_mlp_stats.  Asynchronous on g->stream. */
+int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, float *y);
 /* Cells reconstructed by the learned path and cells that fell back to plain
  * PPM since the previous call (synchronises). */
 int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback);

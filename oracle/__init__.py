@@ -82,6 +82,8 @@ def lib():
         L.oracle_mlp_row_ok.argtypes = [dp, dp, C.c_int]
         L.oracle_mlp_limit.argtypes = [dp, dp]
         L.oracle_learned_values.argtypes = [dp, fp, dp, ip, ip]
+        u8p = C.POINTER(C.c_uint8)
+        L.oracle_learned_rows.argtypes = [dp, fp, dp, dp, u8p, u8p]
         L.oracle_reconstruct_values.argtypes = [dp, dp]
         L.oracle_stage_learned.argtypes = [C.c_void_p, fp, C.c_int, C.c_double, dp, dp, dp, dp,
                                            C.POINTER(Phys), C.c_int, C.c_int, dp, dp, ip]
@@ -362,6 +364,24 @@ def learned_values(P, params):
     nn, nf = C.c_int(), C.c_int()
     lib().oracle_learned_values(_p(P), _p(par, C.c_float), _p(V), C.byref(nn), C.byref(nf))
     return V, nn.value, nf.value
+
+
+def learned_rows(P, params):
+    """The learned reconstruction of one padded block row by row, before any
+    fallback, over the cells (k, j, i) in -1..8 (index (k+1)*100 + (j+1)*10 +
+    (i+1)): network outputs y [1000][7][26] (NaN on flat rows), limited point
+    values val [1000][7][26], the rows' verdicts ok [1000][7] and flat
+    [1000][7] (sigma = 0)."""
+    P = _f64(P)
+    par = np.ascontiguousarray(params, dtype=np.float32)
+    y = np.full((1000, NF, 26), np.nan)
+    val = np.zeros((1000, NF, 26))
+    ok = np.zeros((1000, NF), np.uint8)
+    flat = np.zeros((1000, NF), np.uint8)
+    u8p = C.POINTER(C.c_uint8)
+    lib().oracle_learned_rows(_p(P), _p(par, C.c_float), _p(y), _p(val), ok.ctypes.data_as(u8p),
+                              flat.ctypes.data_as(u8p))
+    return y, val, ok.astype(bool), flat.astype(bool)
 
 
 def reconstruct_values(P):

@@ -279,6 +279,41 @@ void oracle_mlp_limit(const double nb[27], double val[26])
     }
 }
 
+/* The learned reconstruction of every cell -1..8 of one padded block, row by
+ * row and before any fallback.  For cell c (rix order, 10^3 cells) and field
+ * f: flat[c*7+f] = 1 where sigma = 0 (the 26 values are q_c, the network is
+ * not evaluated and y is left untouched); else y[(c*7+f)*26+d] are the
+ * network's outputs (bfloat16-emulating forward), val[(c*7+f)*26+d] the
+ * point values q_c + sigma y_d after the plain limiter, and ok[c*7+f] the
+ * row's FP64 verdict.  A cell falls back to plain PPM when any of its seven
+ * rows fails.  y may be NULL. */
+void oracle_learned_rows(const double *P, const float *par, double *y, double *val, unsigned char *ok,
+                         unsigned char *flat)
+{
+    for (int k = -1; k <= NXC; ++k)
+        for (int j = -1; j <= NXC; ++j)
+            for (int i = -1; i <= NXC; ++i) {
+                const long c = rix(i, j, k);
+                for (int f = 0; f < NFC; ++f) {
+                    const long row = c * NFC + f;
+                    double nb[27], s, x[34], yr[26];
+                    double *v = val + row * 26;
+                    if (oracle_mlp_features(P, i, j, k, f, nb, &s, x)) {
+                        for (int d = 0; d < 26; ++d) v[d] = nb[13];
+                        flat[row] = 1;
+                        ok[row] = 1;
+                        continue;
+                    }
+                    flat[row] = 0;
+                    oracle_mlp_forward(par, 1, x, 1, yr, NULL, NULL, NULL, NULL);
+                    if (y) memcpy(y + row * 26, yr, sizeof yr);
+                    for (int d = 0; d < 26; ++d) v[d] = nb[13] + s * yr[d];
+                    oracle_mlp_limit(nb, v);
+                    ok[row] = (unsigned char)oracle_mlp_row_ok(nb, v, f);
+                }
+            }
+}
+
 /* Point-value table (oracle_reconstruct_values layout) of one padded block
  * by the learned reconstruction with plain-PPM fallback.  Cells needed by the
  * fluxes are the interior and the face-adjacent ghost cells; *needed and
@@ -286,36 +321,34 @@ void oracle_mlp_limit(const double nb[27], double val[26])
  * gets values so the table is complete. */
 void oracle_learned_values(const double *P, const float *par, double *V, int *needed, int *fallback)
 {
-    double *Vp = (double *)malloc(sizeof(double) * RBC * RBC * RBC * 26 * NFC);
+    const long ncell = (long)RBC * RBC * RBC;
+    double *Vp = (double *)malloc(sizeof(double) * ncell * 26 * NFC);
+    double *val = (double *)malloc(sizeof(double) * ncell * NFC * 26);
+    unsigned char *ok = (unsigned char *)malloc((size_t)ncell * NFC);
+    unsigned char *flat = (unsigned char *)malloc((size_t)ncell * NFC);
     oracle_reconstruct_values(P, Vp);
+    oracle_learned_rows(P, par, NULL, val, ok, flat);
     int nn = 0, nf = 0;
     for (int k = -1; k <= NXC; ++k)
         for (int j = -1; j <= NXC; ++j)
             for (int i = -1; i <= NXC; ++i) {
                 int outside = (i < 0 || i >= NXC) + (j < 0 || j >= NXC) + (k < 0 || k >= NXC);
-                double vals[NFC][26];
-                int ok = 1;
-                for (int f = 0; f < NFC; ++f) {
-                    double nb[27], s, x[34], y[26];
-                    if (oracle_mlp_features(P, i, j, k, f, nb, &s, x)) {
-                        for (int d = 0; d < 26; ++d) vals[f][d] = nb[13];
-                        continue;
-                    }
-                    oracle_mlp_forward(par, 1, x, 1, y, NULL, NULL, NULL, NULL);
-                    for (int d = 0; d < 26; ++d) vals[f][d] = nb[13] + s * y[d];
-                    oracle_mlp_limit(nb, vals[f]);
-                    if (!oracle_mlp_row_ok(nb, vals[f], f)) ok = 0;
-                }
                 const long c = rix(i, j, k);
+                int cell_ok = 1;
+                for (int f = 0; f < NFC; ++f) cell_ok &= ok[c * NFC + f];
                 if (outside <= 1) {
                     ++nn;
-                    nf += !ok;
+                    nf += !cell_ok;
                 }
                 for (int d = 0; d < 26; ++d)
                     for (int f = 0; f < NFC; ++f)
-                        V[(c * 26 + d) * NFC + f] = ok ? vals[f][d] : Vp[(c * 26 + d) * NFC + f];
+                        V[(c * 26 + d) * NFC + f] =
+                            cell_ok ? val[(c * NFC + f) * 26 + d] : Vp[(c * 26 + d) * NFC + f];
             }
     free(Vp);
+    free(val);
+    free(ok);
+    free(flat);
     if (needed) *needed = nn;
     if (fallback) *fallback = nf;
 }

@@ -295,7 +295,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         set_schedule(a, resolve_schedule(h, a.nleaf, nst > 1));
         if (h->p.recon == 1) {
             // the network's point values and per-cell verdicts for this launch
-            mlp::MlpInfer m;
+            mlp::MlpInfer m{};
             m.U = Uin;
             m.gmap = g->ghost_map;
             m.wbi = h->mt.wbi;
@@ -1001,6 +1001,33 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
     hipError_t e = hydro_launch_pairs(g->U, g->ghost_map, g->prolong, g->n_prolong, g->n, X, T, valid,
                                       (hipStream_t)g->stream);
     return e == hipSuccess ? HYDRO_OK : hip_fail(h, e, "pairs launch");
+}
+
+int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, float *y) {
+    int rc = check_grid(h, g);
+    if (rc) return rc;
+    if (!g->U || !val || !ok) return fail(h, HYDRO_EINVAL, "null U, val or ok");
+    if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
+    if ((rc = set_device(h))) return rc;
+    mlp::MlpInfer m{};
+    m.U = g->U;
+    m.gmap = g->ghost_map;
+    m.wbi = h->mt.wbi;
+    m.bi = h->mt.bi;
+    m.val = val;
+    m.cell_ok = ok;
+    m.fb_count = h->fb_count;
+    m.leaf0 = 0;
+    m.ts = h->ts;
+    m.lg = h->lg;
+    m.prolong = g->prolong;
+    m.n_prolong = g->n_prolong;
+    m.yraw = y;
+    const int nblk = g->n << h->ts;
+    hipError_t e = hydro_mlp_launch_infer(m, nblk, (hipStream_t)g->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "inference launch");
+    h->mlp_cells += (int64_t)nblk * mlp::NSLOT;
+    return HYDRO_OK;
 }
 
 int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback) {

@@ -62,6 +62,7 @@ struct MlpInfer {
     int ts, lg;                 // blocks per leaf (log2), leaf edge (log2)
     const int32_t *prolong;     // linear-prolongation rows (or null)
     int n_prolong;
+    float *yraw;                // null, or [blocks][7][896][26]: the network's outputs per row
 };
 
 }  // namespace mlp

@@ -629,9 +629,14 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
         // this lane's lines: denormalise, limit, check, store
         const int4 la = otab[q + wz][2], lb = otab[q + wz][3];
         const int loff[4] = {la.x, la.y, la.z, la.w}, lrow[4] = {lb.x, lb.y, lb.z, lb.w};
+        float *yr = m.yraw ? m.yraw + (((size_t)blk * NF + f) * NSLOT + slot) * 26 : nullptr;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (4 * q + t >= 13) continue;
+            if (yr) {
+                yr[lrow[t] & 255] = y[0][t];
+                yr[lrow[t] >> 8] = y[1][t];
+            }
             double R = qc, L = qc;
             if (!flat) {
                 R = qc + sig * (double)y[0][t];

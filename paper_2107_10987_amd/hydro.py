@@ -26,7 +26,7 @@ EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_ghost_map_
            "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
            "hydro_mlp_pairs", "hydro_mlp_stats", "hydro_amax_device",
            "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error",
-           "hydro_step_noalloc")
+           "hydro_step_noalloc", "hydro_mlp_values")
 NOALLOC_MAX_LEAVES = 64
 SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
 NBUCKET = 16
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_mlp_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_double, vp, vp]
     L.hydro_mlp_pairs.argtypes = [vp, C.POINTER(Grid), vp, vp, vp]
     L.hydro_mlp_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.hydro_mlp_values.argtypes = [vp, C.POINTER(Grid), vp, vp, vp]
     L.hydro_amax_device.argtypes = [vp]
     L.hydro_amax_device.restype = vp
     L.hydro_check.argtypes = [vp, vp]
@@ -175,10 +176,6 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
-def _sptr(stream):
-    return None if stream is None else (int(stream.cuda_stream) or None)
-
-
 def step_noalloc(g: "DeviceGrid", dt: float, eta1: float = 1e-3, eta2: float = 1e-1, amax=None,
                  sync: bool = True):
     """One SSP-RK2 step of g (8^3 leaves, at most NOALLOC_MAX_LEAVES) through
@@ -190,6 +187,10 @@ def step_noalloc(g: "DeviceGrid", dt: float, eta1: float = 1e-3, eta2: float = 1
                               int(bool(sync)))
     if rc:
         raise HydroError(rc, L.hydro_last_error(None).decode())
+
+
+def _sptr(stream):
+    return None if stream is None else (int(stream.cuda_stream) or None)
 
 
 class Hydro:
@@ -306,6 +307,17 @@ class Hydro:
         V = t.empty(n, dtype=t.uint8, device=g.U.device)
         self._check(self.L.hydro_mlp_pairs(self.h, C.byref(g.c), _ptr(X), _ptr(T), _ptr(V)))
         return X, T, V
+
+    def mlp_values(self, g: "DeviceGrid", want_y: bool = False):
+        """The inference pre-pass alone: (val [blocks][7][26][896] float64,
+        ok [blocks][896] uint8, y [blocks][7][896][26] float32 or None)."""
+        t = self.torch
+        nb = g.n * (self.leaf_edge // NX) ** 3
+        val = t.empty((nb, NF, 26, 896), dtype=t.float64, device=g.U.device)
+        ok = t.empty((nb, 896), dtype=t.uint8, device=g.U.device)
+        y = t.full((nb, NF, 896, 26), float("nan"), dtype=t.float32, device=g.U.device) if want_y else None
+        self._check(self.L.hydro_mlp_values(self.h, C.byref(g.c), _ptr(val), _ptr(ok), _ptr(y)))
+        return val, ok, y
 
     def mlp_stats(self):
         c, f = C.c_int64(), C.c_int64()

@@ -32,8 +32,8 @@ def field_err(g, o):
                      for f in range(7)])
 
 
-def _box_scale(ora, U, size):
-    P = np.abs(ora.padded(U))                                    # [n][7][14][14][14]
+def _box_scale(ora, U, size, l0=0, l1=None):
+    P = np.abs(ora.padded(U, l0, l1))                            # [l1-l0][7][14][14][14]
     S = P.copy()
     mom = np.sqrt(2.0 * P[:, 0] * P[:, 4])
     for f in (1, 2, 3):
@@ -42,12 +42,13 @@ def _box_scale(ora, U, size):
     return M.reshape(M.shape[0], 7, -1)
 
 
-def local_scale(ora, Uin, want, extra=(), size=5):
-    """Per-cell, per-field scale [n][7][512] (see the module docstring)."""
-    M = _box_scale(ora, Uin, size)
+def local_scale(ora, Uin, want, extra=(), size=5, l0=0, l1=None):
+    """Per-cell, per-field scale [l1-l0][7][512] of leaves [l0, l1) (see the
+    module docstring)."""
+    M = _box_scale(ora, Uin, size, l0, l1)
     M = np.maximum(M, np.abs(np.asarray(want)).reshape(M.shape))
     for X in extra:
-        M = np.maximum(M, _box_scale(ora, X, size))
+        M = np.maximum(M, _box_scale(ora, X, size, l0, l1))
     return M
 
 
@@ -58,10 +59,11 @@ def elem_err(g, o, scale):
     return r.max(axis=(0, 2))
 
 
-def check(g, o, ora, Uin, extra=(), size=5, tol=TOL, elem_tol=ELEM_TOL, label=""):
-    """Assert both bounds; returns (field_err, elem_err)."""
+def check(g, o, ora, Uin, extra=(), size=5, tol=TOL, elem_tol=ELEM_TOL, label="", l0=0, l1=None):
+    """Assert both bounds on leaves [l0, l1) (g and o hold just those);
+    returns (field_err, elem_err)."""
     fe = field_err(g, o)
-    ee = elem_err(g, o, local_scale(ora, Uin, o, extra, size))
+    ee = elem_err(g, o, local_scale(ora, Uin, o, extra, size, l0, l1))
     print(f"{label} per-field {np.array2string(fe, precision=2)} "
           f"per-element {np.array2string(ee, precision=2)}", flush=True)
     assert np.all(fe <= tol), (label, fe)

@@ -197,14 +197,16 @@ def test_learned_step_conserves_and_tracks_oracle(torch, trained):
         assert abs(got[:, f].sum() - U[:, f].sum()) <= 1e-14 * np.abs(U[:, f]).sum()
     Uo, _, fbo = o.step_learned(trained, dt, U)
     Up, _ = o.step(dt, U)
-    dev_oracle = np.abs(got - Uo).max() / np.abs(Uo).max()
-    dev_plain = np.abs(got - Up).max() / np.abs(Up).max()
-    print(f"fallback gpu {fb}/{cells}, oracle {int(fbo.sum())}; max rel dev vs learned oracle "
-          f"{dev_oracle:.2e}, vs plain {dev_plain:.2e}", flush=True)
+    import parity
+    dev_oracle = parity.field_err(got, Uo)
+    dev_plain = parity.field_err(got, Up)
+    print(f"fallback gpu {fb}/{cells}, oracle {int(fbo.sum())}; per-field rel dev vs learned oracle "
+          f"{np.array2string(dev_oracle, precision=2)}, vs plain {np.array2string(dev_plain, precision=2)}",
+          flush=True)
     # bfloat16 networks on both sides differ in accumulation order, so a few
     # borderline cells can take different branches of the check
     assert abs(fb - int(fbo.sum())) <= max(4, 0.02 * cells)
-    assert dev_oracle <= 1e-3
+    assert np.all(dev_oracle <= 1e-4), dev_oracle
 
 
 def test_gain_report_polytrope(torch, trained):

@@ -174,3 +174,40 @@ def test_learned_step_conserves(oracle_mod):
         assert abs(U1[:, f].sum() - w.U[:, f].sum()) <= 1e-14 * np.abs(w.U[:, f]).sum()
     for f in (1, 2, 3):
         assert abs(U1[:, f].sum()) <= 1e-14 * max(np.abs(U1[:, f]).sum(), 1e-300)
+
+
+def test_rows_are_the_table_before_fallback(oracle_mod):
+    """learned_rows exposes the rows learned_values is assembled from: a
+    row's values are the network's outputs de-normalised and limited, its
+    verdict the acceptance test of those values, a flat row is q_c, and the
+    table takes a cell's learned values exactly when all seven rows pass.
+    A constant-output network (zero output weights) gives y = b3 exactly."""
+    w = blast_single_leaf()
+    o = oracle_mod.Oracle(w.tree, w.gamma, w.omega)
+    U, _ = o.step(o.dt(w.U), w.U)
+    P = o.padded(U)[0]
+    p = _params(5, 0.3)
+    p[6400:8064] = 0.0
+    p[8064:] = np.random.default_rng(9).uniform(-0.6, 0.6, 26).astype(np.float32)
+    y, val, ok, flat = oracle_mod.learned_rows(P, p)
+    V, nn, nf = oracle_mod.learned_values(P, p)
+    Vp = oracle_mod.reconstruct_values(P)
+    assert nn == 896
+    rng = np.random.default_rng(10)
+    for c in rng.choice(1000, 60, replace=False):
+        k, j, i = c // 100 - 1, (c // 10) % 10 - 1, c % 10 - 1
+        for f in range(7):
+            nb, s, x = oracle_mod.mlp_features(P, i, j, k, f)
+            assert flat[c, f] == (x is None)
+            if x is None:
+                assert np.all(val[c, f] == nb[13]) and ok[c, f]
+                continue
+            assert np.array_equal(y[c, f], p[8064:].astype(np.float64))
+            v = oracle_mod.mlp_limit(nb, nb[13] + s * y[c, f])
+            assert np.array_equal(val[c, f], v)
+            assert ok[c, f] == oracle_mod.mlp_row_ok(nb, v, f)
+        want = val[c].T if ok[c].all() else Vp[c]
+        assert np.array_equal(V[c], want)
+    needed = [c for c in range(1000)
+              if sum(v < 0 or v > 7 for v in (c % 10 - 1, (c // 10) % 10 - 1, c // 100 - 1)) <= 1]
+    assert nf == sum(not ok[c].all() for c in needed)
