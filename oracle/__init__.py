@@ -175,7 +175,9 @@ class Oracle:
         """One stage over leaves [l0, l1); returns (Uout, amax) for those leaves."""
         Uin = _f64(Uin)
         Un = Uin if Un is None else _f64(Un)
-        Uout = np.zeros_like(Uin)
+        # every value of the returned leaves is written; the rest of the mesh
+        # is never touched (no full-mesh memset per call on a leaf range)
+        Uout = np.empty_like(Uin)
         amax = np.zeros(self.n)
         L = lib()
 
@@ -231,7 +233,7 @@ class Oracle:
         par = np.ascontiguousarray(params, dtype=np.float32)
         Uin = _f64(Uin)
         Un = Uin if Un is None else _f64(Un)
-        Uout = np.zeros_like(Uin)
+        Uout = np.empty_like(Uin)   # (as in stage)
         amax = np.zeros(self.n)
         fb = np.zeros(self.n, dtype=np.int32)
         L = lib()

@@ -80,10 +80,11 @@ double opcount_point_flux(int n, const double *ul, const double *ur, const doubl
     return a.v;
 }
 
-// L(U) of one padded block (flux divergence, source); the counts include the
-// oracle's reconstruction of every cell -1..8 per axis.
+// L(U) of one padded block (flux divergence, source), the new scheme or (with
+// centre_only) the old face-centre one; the counts include the oracle's
+// reconstruction of all 13 lines at every cell -1..8 per axis.
 void opcount_leaf_rhs(const double *P, double dx, const double *origin, double gamma,
-                      double omega, double eta1, double *dU) {
+                      double omega, double eta1, int centre_only, double *dU) {
     const long np = 7L * 2744;
     cd *Pc = (cd *)malloc(sizeof(cd) * np);
     cd *dUc = (cd *)malloc(sizeof(cd) * 7 * 512);
@@ -94,7 +95,7 @@ void opcount_leaf_rhs(const double *P, double dx, const double *origin, double g
     ph.omega = cd(omega);
     ph.eta1 = cd(eta1);
     ph.eta2 = cd(0.1);
-    ph.centre_only = 0;
+    ph.centre_only = centre_only;
     ph.reflux = 0;
     cd am;
     oracle_leaf_rhs(Pc, cd(dx), org, &ph, dUc, &am);

@@ -48,7 +48,7 @@ def _lib():
     L.opcount_ppm.argtypes = [dp, dp]
     L.opcount_point_flux.argtypes = [C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp]
     L.opcount_point_flux.restype = C.c_double
-    L.opcount_leaf_rhs.argtypes = [dp, C.c_double, dp, C.c_double, C.c_double, C.c_double, dp]
+    L.opcount_leaf_rhs.argtypes = [dp, C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
     return L
 
 
@@ -105,7 +105,7 @@ def counts(gamma=5.0 / 3.0, omega=0.1):
     # whole L(U) of a leaf as the oracle computes it
     dU = np.zeros((7, 512))
     L.opcount_reset()
-    L.opcount_leaf_rhs(_p(P), 1.0 / 64, _p(np.zeros(3)), gamma, omega, 1e-3, _p(dU))
+    L.opcount_leaf_rhs(_p(P), 1.0 / 64, _p(np.zeros(3)), gamma, omega, 1e-3, 0, _p(dU))
     rhs = _read(L)
     oracle_lines = ORACLE_RECON_CELLS * 13 * 7
     needed_lines = NEEDED_RECON_LINES * 7
@@ -119,8 +119,38 @@ def counts(gamma=5.0 / 3.0, omega=0.1):
     return parts, per_cell
 
 
+# the old face-centre scheme: the axis line of every interior cell in each
+# direction and, at each face-adjacent ghost cell, the axis line normal to its
+# slab; one flux point per face
+OLD_NEEDED_RECON_LINES = 512 * 3 + 384 * 1         # 3.75 per cell
+OLD_POINTS_PER_LEAF = 3 * 9 * 64
+
+
+def counts_old(gamma=5.0 / 3.0, omega=0.1):
+    """Flops per interior cell-update of one stage (mean of the two stages)
+    of the old scheme: the oracle's L(U) with one point per face, less the
+    lines it reconstructs beyond the 3.75 per cell and field the scheme needs
+    and less the multiplications by the unit face weight."""
+    L = _lib()
+    P = smooth_block(gamma=gamma)
+    q = np.ascontiguousarray(P[0, 3, 3, 3:8])
+    lr = np.zeros(2)
+    L.opcount_reset()
+    L.opcount_ppm(_p(q), _p(lr))
+    ppm = _read(L)
+    dU = np.zeros((7, 512))
+    L.opcount_reset()
+    L.opcount_leaf_rhs(_p(P), 1.0 / 64, _p(np.zeros(3)), gamma, omega, 1e-3, 1, _p(dU))
+    rhs = _read(L)
+    surplus = (ORACLE_RECON_CELLS * 13 - OLD_NEEDED_RECON_LINES) * 7
+    rhs_needed = rhs[0] - surplus * ppm[0] - OLD_POINTS_PER_LEAF * 7
+    combine = (2 * 7 + (4 * 7 + 10)) / 2.0
+    return rhs_needed / 512.0 + combine
+
+
 if __name__ == "__main__":
     parts, per_cell = counts()
     for k, v in parts.items():
         print(k, v)
     print("flops per cell-update", per_cell)
+    print("old scheme: flops per cell-update", counts_old())

@@ -849,6 +849,7 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
         float best_ms = 1e30f;
         int best = HYDRO_SCHED_COLUMN;
         for (int sc = HYDRO_SCHED_FACE; sc <= HYDRO_SCHED_TILED && rc == HYDRO_OK; ++sc) {
+            if (sc == HYDRO_SCHED_FACE && h->p.recon == 1) continue;   // no learned variant (runs the column walk)
             h->p.schedule = sc;
             const int reps = size >= 256 ? 3 : 10;
             rc = run_stage(h, &sub, 1, 0.0, g->U, g->U, h->U1, h->amax, 0, nullptr, false);   // warm
@@ -1006,7 +1007,8 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
 int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, float *y) {
     int rc = check_grid(h, g);
     if (rc) return rc;
-    if (!g->U || !val || !ok) return fail(h, HYDRO_EINVAL, "null U, val or ok");
+    if (!g->U || !val != !ok) return fail(h, HYDRO_EINVAL, "null U, or only one of val and ok");
+    if (!val && !h->mlp_val) return fail(h, HYDRO_EINVAL, "val is NULL and the handle has no learned workspace");
     if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
     if ((rc = set_device(h))) return rc;
     mlp::MlpInfer m{};
@@ -1014,8 +1016,8 @@ int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, 
     m.gmap = g->ghost_map;
     m.wbi = h->mt.wbi;
     m.bi = h->mt.bi;
-    m.val = val;
-    m.cell_ok = ok;
+    m.val = val ? val : h->mlp_val;
+    m.cell_ok = ok ? ok : h->mlp_ok;
     m.fb_count = h->fb_count;
     m.leaf0 = 0;
     m.ts = h->ts;

@@ -308,9 +308,13 @@ class Hydro:
         self._check(self.L.hydro_mlp_pairs(self.h, C.byref(g.c), _ptr(X), _ptr(T), _ptr(V)))
         return X, T, V
 
-    def mlp_values(self, g: "DeviceGrid", want_y: bool = False):
+    def mlp_values(self, g: "DeviceGrid", want_y: bool = False, into_handle: bool = False):
         """The inference pre-pass alone: (val [blocks][7][26][896] float64,
-        ok [blocks][896] uint8, y [blocks][7][896][26] float32 or None)."""
+        ok [blocks][896] uint8, y [blocks][7][896][26] float32 or None);
+        into_handle: into the handle's own workspace, returns nothing."""
+        if into_handle:
+            self._check(self.L.hydro_mlp_values(self.h, C.byref(g.c), None, None, None))
+            return None
         t = self.torch
         nb = g.n * (self.leaf_edge // NX) ** 3
         val = t.empty((nb, NF, 26, 896), dtype=t.float64, device=g.U.device)
