@@ -187,7 +187,7 @@ def _per_dispatch(rows, counter: str):
 
 def _short(name: str):
     import re
-    m = re.search(r"\b(stage_kernel\w*|mlp_infer_kernel)\(", name)
+    m = re.search(r"\b(stage_kernel\w*|mlp_infer_kernel)(?:<[^>(]*>)?\(", name)
     return m.group(1) if m else None
 
 

@@ -38,6 +38,25 @@ __host__ __device__ inline int slot_of(int i, int j, int k) {
     return 512 + 64 * (k < 0 ? 4 : 5) + i + 8 * j;
 }
 
+// The plain limiter on a predicted pair of one line (R at +d, L at -d), the
+// cell value qc and its neighbours nbR (at +d) and nbL (at -d): each value
+// clamped between the cell and its neighbour in that direction, then the PPM
+// monotonicity constraint on the pair (unfused FP64).  min/max clamps carry a
+// NaN prediction to a bound; the pre-pass's check fails it.
+__device__ __forceinline__ void learned_limit(double qc, double nbR, double nbL, double &R, double &L) {
+    const double loR = fmin(qc, nbR), hiR = fmax(qc, nbR);
+    const double loL = fmin(qc, nbL), hiL = fmax(qc, nbL);
+    double r = fmin(fmax(R, loR), hiR), l = fmin(fmax(L, loL), hiL);
+    const bool ext = (r - qc) * (qc - l) <= 0.0;
+    const double D = r - l, M6 = 6.0 * (qc - 0.5 * (l + r));
+    const double DM = D * M6, DD = D * D;
+    const bool lowL = DM > DD, lowR = !lowL & (DM < -DD);
+    const double ln = lowL ? 3.0 * qc - 2.0 * r : l;
+    const double rn = lowR ? 3.0 * qc - 2.0 * l : r;
+    L = ext ? qc : ln;
+    R = ext ? qc : rn;
+}
+
 struct MlpTrain {
     float *par, *m, *v, *grad;          // [NPAR]
     uint16_t *wb, *wbT;                 // bf16 MFMA copies

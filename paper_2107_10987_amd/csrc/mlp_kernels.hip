@@ -428,17 +428,8 @@ __device__ __forceinline__ bool limit_check_line(double qc, double nbR, double n
     bool ok = (R == R) & (L == L);
     const double loR = fmin(qc, nbR), hiR = fmax(qc, nbR);
     const double loL = fmin(qc, nbL), hiL = fmax(qc, nbL);
-    double r = fmin(fmax(R, loR), hiR), l = fmin(fmax(L, loL), hiL);
-    {
-        const bool ext = (r - qc) * (qc - l) <= 0.0;
-        const double D = r - l, M6 = 6.0 * (qc - 0.5 * (l + r));
-        const double DM = D * M6, DD = D * D;
-        const bool lowL = DM > DD, lowR = !lowL & (DM < -DD);
-        const double ln = lowL ? 3.0 * qc - 2.0 * r : l;
-        const double rn = lowR ? 3.0 * qc - 2.0 * l : r;
-        l = ext ? qc : ln;
-        r = ext ? qc : rn;
-    }
+    double r = R, l = L;
+    learned_limit(qc, nbR, nbL, r, l);
     ok = ok & (r >= loR) & (r <= hiR) & (l >= loL) & (l <= hiL);
     if (f == RHO || f == EGAS || f == TAU) ok = ok & (r > 0.0) & (l > 0.0);
     if (f == SPC) ok = ok & (r >= 0.0) & (l >= 0.0);

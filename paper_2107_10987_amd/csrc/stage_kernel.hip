@@ -587,9 +587,10 @@ __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
     return k < 13 ? k : k - 1;
 }
 
+template <bool LEARNED>
 __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy, int dz,
                                           const ValSrc &src, double pos[NF], double neg[NF]) {
-    if (src.val) {
+    if (LEARNED && src.val) {
         const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -638,7 +639,10 @@ __device__ __forceinline__ double point_flux_acc(int n, const double UL[NF], con
 
 // Flux difference F(face above) - F(face below) along axis N (run-time, so
 // one copy of the walk serves all three axes) of this lane's cell, for
-// column `col` and cell index `cell` in -1..8.
+// column `col` and cell index `cell` in -1..8.  LEARNED: the learned
+// reconstruction's values where the pre-pass passed the cell (a separate
+// instantiation, so that the plain walk carries none of its registers).
+template <bool LEARNED>
 __device__ __forceinline__ void column_axis(int N, const double *P, int col, int cell, double dx,
                                             double ox, double oy, double oz, const Phys &ph,
                                             const StageArgs &a, int leaf, bool live, double dsum[NF],
@@ -650,7 +654,7 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     const int bk = (N == 2) ? cell : c2;
     const int cB = pidx(bi, bj, bk);
     ValSrc src{nullptr};
-    if (a.mlp_val) {
+    if (LEARNED && a.mlp_val) {
         const int slot = mlp::slot_of(bi, bj, bk);
         if (a.mlp_ok[(size_t)leaf * mlp::NSLOT + slot])
             src.val = a.mlp_val + (size_t)leaf * NF * 26 * mlp::NSLOT + slot;
@@ -671,7 +675,7 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     auto qy = [&](int a, int b) { return yB + 0.5 * (double)((N == 1) ? -1 : ((N == 0) ? a : b)) * dx; };
     {   // the face-normal line serves the face centre
         double pos[NF], neg[NF], prev[NF];
-        line_vals(P, cB, dirx(0, 0), diry(0, 0), dirz(0, 0), src, pos, neg);
+        line_vals<LEARNED>(P, cB, dirx(0, 0), diry(0, 0), dirz(0, 0), src, pos, neg);
 #pragma unroll
         for (int f = 0; f < NF; ++f) prev[f] = shfl_up1(pos[f]);
         if (face) {
@@ -688,8 +692,8 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
         const int tb = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
         const double w = (p < 2) ? 4.0 / 36.0 : 1.0 / 36.0;
         double pos1[NF], neg1[NF], pos2[NF], neg2[NF];
-        line_vals(P, cB, dirx(ta, tb), diry(ta, tb), dirz(ta, tb), src, pos1, neg1);
-        line_vals(P, cB, dirx(-ta, -tb), diry(-ta, -tb), dirz(-ta, -tb), src, pos2, neg2);
+        line_vals<LEARNED>(P, cB, dirx(ta, tb), diry(ta, tb), dirz(ta, tb), src, pos1, neg1);
+        line_vals<LEARNED>(P, cB, dirx(-ta, -tb), diry(-ta, -tb), dirz(-ta, -tb), src, pos2, neg2);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             pos1[f] = shfl_up1(pos1[f]);
@@ -734,13 +738,14 @@ struct ColLane {
 // Flux differences along this lane's axis N of one leaf into that axis's
 // workspace slice of W (linear cell index); folds the lane's signal speeds
 // into smax.
+template <bool LEARNED>
 __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const double *P,
                                                const ColLane &L, int leaf, double *W, double &smax) {
     double dx, ox, oy, oz;
     block_geometry(a, leaf, dx, ox, oy, oz);
     double d[NF];
     double sm = 0.0;
-    column_axis(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
+    column_axis<LEARNED>(N, P, L.col, L.cell, dx, ox, oy, oz, a.ph, a, leaf, L.live, d, sm);
     smax = L.live && sm > smax ? sm : smax;
     if (L.live && L.cell >= 0 && L.cell < NX && a.stage != 0) {
         const int c = (N == 0) ? (L.c2 * NX + L.c1) * NX + L.cell
@@ -772,6 +777,7 @@ __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, co
 // LDS (which starts at the wave count), so the tasks spread evenly over the
 // SIMDs whatever the order the waves run in.  Columns of one axis write that
 // axis's slice of W only, so no barrier separates the axes.
+template <bool LEARNED>
 __device__ __forceinline__ void walk_columns(const StageArgs &a, const double *P, int leaf,
                                              double *W, int first, int count, int *next_task,
                                              int tid, double &smax) {
@@ -781,7 +787,7 @@ __device__ __forceinline__ void walk_columns(const StageArgs &a, const double *P
 #pragma unroll 1
     while (task < ntask) {
         const ColLane L(lane, task, first, count);
-        col_axis_to_ws(L.axis, a, P, L, leaf, W, smax);
+        col_axis_to_ws<LEARNED>(L.axis, a, P, L, leaf, W, smax);
         int t = 0;
         if (lane == 0) t = atomicAdd(next_task, 1);
         task = __builtin_amdgcn_readfirstlane(t);
@@ -799,6 +805,7 @@ __device__ __forceinline__ void block_max(double smax, double *red, int tid) {
 
 // One leaf per workgroup, all three axes, then the leaf is finished from
 // the three slices.
+template <bool LEARNED>
 __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __shared__ double P[NF * NP];
     __shared__ int next_task;
@@ -809,7 +816,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     __syncthreads();
     double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
     double smax = 0.0;
-    walk_columns(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
+    walk_columns<LEARNED>(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
     __syncthreads();   // every slice of W is written
     col_finish_leaf(a, leaf, W, tid, NTC);
     block_max(smax, P, tid);
@@ -821,6 +828,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
 // the workgroup that completes a leaf's last axis finishes the leaf, so a
 // small batch spreads over three times as many compute units.  The last
 // workgroup to leave resets the queue for the next launch.
+template <bool LEARNED>
 __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) {
     __shared__ double P[NF * NP];
     __shared__ int item_s, last_s, next_task;
@@ -842,7 +850,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         double *W = a.dscr + (size_t)leaf * 3 * NF * NC;
         double smax = 0.0;
         // one tile: all 192 columns; three: the 64 columns of axis `tile`
-        walk_columns(a, P, leaf, W, T == 1 ? 0 : tile * NX * NX, T == 1 ? 3 * NX * NX : NX * NX,
+        walk_columns<LEARNED>(a, P, leaf, W, T == 1 ? 0 : tile * NX * NX, T == 1 ? 3 * NX * NX : NX * NX,
                      &next_task, tid, smax);
         if (T == 1) {
             __syncthreads();   // every slice of W is written
@@ -994,12 +1002,18 @@ hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(stage_kernel, dim3(a.nleaf), dim3(NT), 0, s, a);
         break;
     case KERNEL_COLUMN:
-        hipLaunchKernelGGL(stage_kernel_col, dim3(a.nleaf), dim3(NTC), 0, s, a);
+        if (a.mlp_val)
+            hipLaunchKernelGGL(stage_kernel_col<true>, dim3(a.nleaf), dim3(NTC), 0, s, a);
+        else
+            hipLaunchKernelGGL(stage_kernel_col<false>, dim3(a.nleaf), dim3(NTC), 0, s, a);
         break;
     default: {   // persistent column walk
         const int items = a.nleaf * a.tiles;
         const int grid = items < a.grid_limit ? items : a.grid_limit;
-        hipLaunchKernelGGL(stage_kernel_col_persistent, dim3(grid), dim3(NTC), 0, s, a);
+        if (a.mlp_val)
+            hipLaunchKernelGGL(stage_kernel_col_persistent<true>, dim3(grid), dim3(NTC), 0, s, a);
+        else
+            hipLaunchKernelGGL(stage_kernel_col_persistent<false>, dim3(grid), dim3(NTC), 0, s, a);
     }
     }
     return hipGetLastError();

@@ -433,7 +433,13 @@ def test_trained_network_learned_stage_polytrope(torch, trained):
     finally:
         hy.close()
     o1, oa1, ofb1 = case.ora.stage_learned(trained, 1, dt, case.U, l0=l0, l1=l1)
-    fe = parity.field_err(U1h, o1)
+    # per field against the field's largest value; the momenta against the
+    # largest momentum component (the star rotates about z, so its z momentum
+    # is only what one stage of pressure forces gives it)
+    g3, o3 = U1h.reshape(48, 7, -1), o1.reshape(48, 7, -1)
+    scale = np.abs(o3).max(axis=(0, 2))
+    scale[1:4] = scale[1:4].max()
+    fe = np.abs(g3 - o3).max(axis=(0, 2)) / scale
     da = np.abs(am1 - oa1).max() / oa1.max()
     print(f"trained stage 1: per-field {np.array2string(fe, precision=2)}; signal speed {da:.2e}; "
           f"oracle fallback cells {int(ofb1.sum())}", flush=True)
