@@ -185,10 +185,14 @@ def _per_dispatch(rows, counter: str):
     return dict(sorted(out.items()))
 
 
-def _short(name: str):
+def _short(name: str, template: bool = False):
+    """This library's kernel name in a rocprofv3 kernel name (with its
+    template arguments if `template`), or None."""
     import re
-    m = re.search(r"\b(stage_kernel\w*|mlp_infer_kernel)(?:<[^>(]*>)?\(", name)
-    return m.group(1) if m else None
+    m = re.search(r"\b(stage_kernel\w*|mlp_infer_kernel)(<[^>(]*>)?\(", name)
+    if not m:
+        return None
+    return m.group(1) + (m.group(2) or "") if template else m.group(1)
 
 
 def reduce_trace(d: str) -> str:
@@ -202,7 +206,7 @@ def reduce_trace(d: str) -> str:
     for fn in files:
         with open(fn) as f:
             for r in csv.DictReader(f):
-                k = _short(r["Kernel_Name"]) or r["Kernel_Name"].split("(")[0]
+                k = _short(r["Kernel_Name"], template=True) or r["Kernel_Name"].split("(")[0]
                 if not (k.startswith("stage_kernel") or k.startswith("mlp_") or k.startswith("dt_kernel")
                         or k.startswith("reflux")):
                     continue
