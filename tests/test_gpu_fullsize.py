@@ -1,8 +1,9 @@
-"""Full-size check: the binary-star workload of 32768 leaves (16,777,216
-cells, the paper's problem size) on a 4-level octree in the rotating frame,
-one stage on the GPU in the persistent/tiled launch configuration, compared
-with the oracle on sampled leaves that the oracle computes one by one from
-the same input, plus properties that hold at any size."""
+"""Full-size checks on the binary-star workload of 32768 leaves (16,777,216
+cells, the paper's problem size) on a 4-level octree in the rotating frame:
+one stage in uneven launches (autotuned and tiled schedules) against the
+oracle on sampled leaves it computes one by one from the same input, and the
+benchmark's headline configuration (one launch per stage, a graph-captured
+step with the time step on the device) against a whole oracle step."""
 import numpy as np
 import pytest
 
@@ -57,3 +58,48 @@ def test_binary_32768_stage_sampled_parity(torch, binary, schedule):
             scale = max(np.abs(ref[:, f]).max(), 1e-300)
             assert np.abs(got[:, f] - ref[:, f]).max() <= TOL * scale, (l0, f)
         assert np.abs(am[l0:l0 + 8] - ao).max() <= TOL * ao.max()
+
+
+def test_binary_32768_headline_configuration_step_parity(torch, binary):
+    """The configuration bench.py times for its headline: every leaf in one
+    launch per stage (the schedule the built-in rule picks for 32,768 leaves),
+    a whole SSP-RK2 step captured in a HIP graph with the time step read from
+    and written to device memory.  Against one oracle step of the whole mesh
+    (fed the same dt): every element within the FP64 parity bound per field,
+    the element-wise bound on sampled leaf ranges, and the device's next time
+    step equal to the oracle's to 1e-12."""
+    import oracle
+    import parity
+    from paper_2107_10987_amd.hydro import Hydro
+    w = binary
+    print("case: binary-32768, one launch per stage, graph step with device dt", flush=True)
+    hy = Hydro(max_leaves=w.n, schedule="auto")
+    try:
+        s = torch.cuda.Stream()
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, stream=s)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hy.graph_capture(g, w.cfl, dt_dev, 1)
+        hy.dt(g, w.cfl, dt_dev)
+        s.synchronize()
+        dt0 = float(dt_dev.item())
+        hy.graph_launch(s)
+        s.synchronize()
+        hy.check(s)
+        got = g.U.cpu().numpy()
+        dt1 = float(dt_dev.item())
+    finally:
+        hy.close()
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    dto = o.dt(w.U, w.cfl)
+    assert abs(dt0 - dto) <= 1e-12 * dto
+    Uo, am = o.step(dt0, w.U)
+    dto1 = float(w.cfl * np.min(w.tree.dx / am))
+    assert abs(dt1 - dto1) <= 1e-12 * dto1, (dt1, dto1)
+    fe = parity.field_err(got, Uo)
+    print(f"binary step per-field {np.array2string(fe, precision=2)}", flush=True)
+    assert np.all(fe <= TOL), fe
+    rng = np.random.default_rng(12)
+    for l0 in np.sort(rng.choice(w.n - 8, 8, replace=False)):
+        l0 = int(l0)
+        parity.check(got[l0:l0 + 8], Uo[l0:l0 + 8], o, w.U, size=7, l0=l0, l1=l0 + 8,
+                     label=f"binary leaves [{l0}, {l0 + 8})")
