@@ -29,7 +29,7 @@ struct hydro_t {
     int rk = 2;
     int ts = 0, lg = 3;        // 8^3 blocks per leaf (log2), leaf edge (log2)
     double *dscr = nullptr;    // column walk: [max_leaves][3][7][512]
-    int *queue = nullptr;      // persistent launches: [1 + NSIDE][2], one per stream
+    int *queue = nullptr;      // persistent launches: [1 + NSIDE][QUEUE_INTS], one per stream
     // the launches of one stage run on the caller's stream and NSIDE side
     // streams (default priority), forked from and joined back to it by events
     hipStream_t side[NSIDE] = {};
@@ -291,7 +291,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
         if (a.nleaf == 0) continue;
         const int j = k++ % nst;
         const hipStream_t st = j == 0 ? s : h->side[j - 1];
-        a.queue = h->queue + 2 * j;
+        a.queue = h->queue + QUEUE_INTS * j;
         set_schedule(a, resolve_schedule(h, a.nleaf, nst > 1));
         if (h->p.recon == 1) {
             // the network's point values and per-cell verdicts for this launch
@@ -655,7 +655,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (e == hipSuccess && h->rk == 3) e = hipMalloc((void **)&h->U2, n * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->dscr, n * 3 * LEAF_STRIDE * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->amax, n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->queue, 2 * (1 + NSIDE) * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->queue, QUEUE_INTS * (1 + NSIDE) * sizeof(int));
     for (int i = 0; i < NSIDE && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming);
@@ -665,7 +665,7 @@ int hydro_create(const hydro_params *p, hydro_t **out) {
     if (e == hipSuccess) e = hipMalloc((void **)&h->tile_amax, n * 3 * sizeof(double));
     if (e == hipSuccess && p->reflux) e = hipMalloc((void **)&h->bflux, n * BFLUX_STRIDE * sizeof(double));
     if (e == hipSuccess) e = alloc_mlp(h, n);
-    if (e == hipSuccess) e = hipMemset(h->queue, 0, 2 * (1 + NSIDE) * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(h->queue, 0, QUEUE_INTS * (1 + NSIDE) * sizeof(int));
     if (e == hipSuccess) e = hipMemset(h->leaf_done, 0, n * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&h->status, sizeof(Status));
     if (e == hipSuccess) e = hipMemset(h->status, 0, sizeof(Status));

@@ -58,7 +58,8 @@ struct StageArgs {
     // persistent column walk
     int tiles;                // 1: whole leaves; 3: one axis per item
     int grid_limit;           // workgroups of a persistent launch
-    int *queue;               // [2]: next item, workgroups finished (zero between launches)
+    int *queue;               // [QUEUE_INTS]: next item of each XCD's range, workgroups
+                              // finished (zero between launches)
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
     // learned reconstruction (null: plain PPM)
@@ -176,6 +177,12 @@ struct RefluxArgs {
 
 enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
 
+// XCDs of the chip (workgroups are dispatched round-robin over them) and the
+// persistent queue's counters: one per XCD's item range, then the count of
+// finished workgroups.
+constexpr int NXCD = 8;
+constexpr int QUEUE_INTS = 16;
+
 // Leaf (within a launch of n leaves, one workgroup each) of workgroup b.
 // Workgroups are dispatched round-robin over the chip's 8 XCDs (b runs on
 // XCD b % 8), each with its own L2; XCD x gets a contiguous range of the
@@ -183,7 +190,6 @@ enum Kernel { KERNEL_FACE = 0, KERNEL_COLUMN = 1, KERNEL_PERSISTENT = 2 };
 // reads mostly belong to leaves its own L2 has just seen.  A bijection on
 // [0, n); every leaf's result is independent of which workgroup computes it.
 __device__ __forceinline__ int xcd_leaf(int b, int n) {
-    constexpr int NXCD = 8;
     const int q = n / NXCD, r = n % NXCD;
     const int x = b % NXCD, k = b / NXCD;
     return x * q + (x < r ? x : r) + k;

@@ -826,18 +826,42 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
 // Persistent workgroups over a queue of (leaf, tile) items.  With one tile a
 // workgroup does whole leaves; with three, an item is one axis of a leaf and
 // the workgroup that completes a leaf's last axis finishes the leaf, so a
-// small batch spreads over three times as many compute units.  The last
-// workgroup to leave resets the queue for the next launch.
+// small batch spreads over three times as many compute units.  Whole leaves
+// come from one counter (a fast compute unit takes more of them).  Axis
+// items are split into one contiguous (Morton) range per XCD, each with its
+// own counter: a workgroup takes items from its XCD's range, so the three
+// axis items of a leaf, which write and read the same workspace slices, and
+// its neighbours' ghost cells stay in one L2; when that range is empty it
+// takes the next items of the other ranges in turn (measured: tiled launches
+// 6-8% faster than with one counter, whole-leaf launches 3-10% slower).  The
+// last workgroup to leave resets the counters for the next launch.
+__device__ __forceinline__ int next_item(int *queue, int items, int xcd) {
+    const int q = items / NXCD, r = items % NXCD;
+    for (int k = 0; k < NXCD; ++k) {
+        const int x = (xcd + k) & (NXCD - 1);
+        const int len = q + (x < r ? 1 : 0);
+        // a device-coherent read skips exhausted ranges without an atomic
+        if (__hip_atomic_load(&queue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) continue;
+        const int i = atomicAdd(&queue[x], 1);
+        if (i < len) return x * q + (x < r ? x : r) + i;
+    }
+    return items;
+}
 template <bool LEARNED>
 __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) {
     __shared__ double P[NF * NP];
     __shared__ int item_s, last_s, next_task;
-    const int tid = threadIdx.x;
+    const int tid0 = threadIdx.x;
     const int T = a.tiles;
     const int items = a.nleaf * T;
     for (;;) {
+        // a per-iteration copy of the thread index the compiler cannot see
+        // through: what the body derives from it is recomputed each item
+        // instead of hoisted out of the loop and kept live across the walk
+        int tid = tid0;
+        asm volatile("" : "+v"(tid));
         if (tid == 0) {
-            item_s = atomicAdd(&a.queue[0], 1);
+            item_s = T == 1 ? atomicAdd(&a.queue[0], 1) : next_item(a.queue, items, (int)(blockIdx.x % NXCD));
             next_task = NTC / 64;
         }
         __syncthreads();
@@ -885,11 +909,10 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
         }
         __syncthreads();   // LDS, item_s and next_task are reused by the next item
     }
-    if (tid == 0) {
+    if (tid0 == 0) {
         __threadfence();
-        if (atomicAdd(&a.queue[1], 1) == (int)gridDim.x - 1) {
-            a.queue[0] = 0;
-            a.queue[1] = 0;
+        if (atomicAdd(&a.queue[NXCD], 1) == (int)gridDim.x - 1) {
+            for (int x = 0; x <= NXCD; ++x) a.queue[x] = 0;
             __threadfence();
         }
     }
