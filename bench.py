@@ -16,7 +16,8 @@ cache.
 
 The same line reports the other workloads: the same binary with the learned
 reconstruction, the 64^3 Sedov blast (512 leaves; the oracle trajectory
-parity case), the same blast as 16^3 leaves, the 4096-leaf rotating
+parity case), the same blast as 16^3 leaves, the Sedov blast at the paper's
+problem size (256^3 as 32,768 leaves), the 4096-leaf rotating
 polytrope in seeded uneven launches (plain and learned), the old face-centre
 scheme on the Sedov blast, each with its own roofline, and the CPU oracle.
 
@@ -528,8 +529,9 @@ def polytrope_legs(torch, args, params):
 
 def sedov_legs(torch, args):
     """The 64^3 Sedov blast as 512 leaves of 8^3 (the trajectory the GPU
-    parity tests follow), the same blast as 64 leaves of 16^3 and with the
-    paper's old face-centre scheme."""
+    parity tests follow), the same blast as 64 leaves of 16^3, at the paper's
+    problem size (256^3, 32,768 leaves) and with the paper's old face-centre
+    scheme."""
     from paper_2107_10987_amd.workloads import sedov_uniform
     out = {}
     w = sedov_uniform(8)
@@ -543,6 +545,13 @@ def sedov_legs(torch, args):
     r = single_launch_leg(torch, args, w16, "sedov64-leaf16", schedule="column")
     r.pop("U")
     out["leaf16"] = r
+    w256 = sedov_uniform(32)
+    w256.name = ("sedov-256^3: the paper's Sedov problem size, 16,777,216 cells as 32,768 leaves of 8^3, "
+                 "outflow, plain PPM, one launch per stage over all leaves")
+    r = single_launch_leg(torch, args, w256, "sedov256", schedule="column")
+    r.pop("U")
+    out["sedov256"] = r
+    del w256
     wo = sedov_uniform(8)
     wo.name = "sedov-64^3 with the old scheme: one flux point per face (the face centre), weight 1"
     r = single_launch_leg(torch, args, wo, "sedov64-old", schedule="column", centre_only=True,

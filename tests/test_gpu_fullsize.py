@@ -60,8 +60,17 @@ def test_binary_32768_stage_sampled_parity(torch, binary, schedule):
         assert np.abs(am[l0:l0 + 8] - ao).max() <= TOL * ao.max()
 
 
-def test_binary_32768_headline_configuration_step_parity(torch, binary):
-    """The configuration bench.py times for its headline: every leaf in one
+@pytest.fixture(scope="module")
+def sedov256():
+    from paper_2107_10987_amd.workloads import sedov_uniform
+    print("case: building the 256^3 Sedov blast (32768 leaves)", flush=True)
+    return sedov_uniform(32)
+
+
+@pytest.mark.parametrize("name", ["binary", "sedov256"])
+def test_headline_configuration_step_parity(torch, request, name):
+    """The configuration bench.py times for its headline (the binary; the
+    256^3 Sedov leg runs the same way): every leaf in one
     launch per stage (the schedule the built-in rule picks for 32,768 leaves),
     a whole SSP-RK2 step captured in a HIP graph with the time step read from
     and written to device memory.  Against one oracle step of the whole mesh
@@ -71,8 +80,8 @@ def test_binary_32768_headline_configuration_step_parity(torch, binary):
     import oracle
     import parity
     from paper_2107_10987_amd.hydro import Hydro
-    w = binary
-    print("case: binary-32768, one launch per stage, graph step with device dt", flush=True)
+    w = request.getfixturevalue(name)
+    print(f"case: {name} (32768 leaves), one launch per stage, graph step with device dt", flush=True)
     hy = Hydro(max_leaves=w.n, schedule="auto")
     try:
         s = torch.cuda.Stream()
@@ -96,10 +105,10 @@ def test_binary_32768_headline_configuration_step_parity(torch, binary):
     dto1 = float(w.cfl * np.min(w.tree.dx / am))
     assert abs(dt1 - dto1) <= 1e-12 * dto1, (dt1, dto1)
     fe = parity.field_err(got, Uo)
-    print(f"binary step per-field {np.array2string(fe, precision=2)}", flush=True)
+    print(f"{name} step per-field {np.array2string(fe, precision=2)}", flush=True)
     assert np.all(fe <= TOL), fe
     rng = np.random.default_rng(12)
     for l0 in np.sort(rng.choice(w.n - 8, 8, replace=False)):
         l0 = int(l0)
         parity.check(got[l0:l0 + 8], Uo[l0:l0 + 8], o, w.U, size=7, l0=l0, l1=l0 + 8,
-                     label=f"binary leaves [{l0}, {l0 + 8})")
+                     label=f"{name} leaves [{l0}, {l0 + 8})")
