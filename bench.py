@@ -92,7 +92,8 @@ def parse(argv=None):
                     help="before anything else, one untimed device copy of this many MiB from a freshly "
                          "written buffer (the reference kernel for HBM counter calibration)")
     ap.add_argument("--profile", default=None,
-                    choices=["binary-plain", "binary-learned", "sedov64", "polytrope-plain", "polytrope-learned"],
+                    choices=["binary-plain", "binary-learned", "sedov64", "sedov256", "polytrope-plain",
+                             "polytrope-learned"],
                     help="run only this workload's kernels, a few eager steps (for counter runs)")
     ap.add_argument("--reduce-trace", metavar="TRACE_DIR",
                     help="per-kernel, per-grid-size dispatch counts and mean durations of a rocprofv3 "
@@ -661,6 +662,8 @@ def profile_mode(torch, args):
         w = binary_star()
     elif name.startswith("polytrope"):
         w = rotating_polytrope()
+    elif name == "sedov256":
+        w = sedov_uniform(32)
     else:
         w = sedov_uniform(8)
     off = None
