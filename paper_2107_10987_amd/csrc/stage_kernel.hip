@@ -390,19 +390,17 @@ __device__ __forceinline__ void store_bflux(const StageArgs &a, int leaf, int n,
 
 // Flux divergence sum dsum (per field, over the three axes) -> L(U), the
 // rotating-frame source, the stage combine, the tracer resync and the store
-// of one interior cell; non-physical results are reported in a.status.
-__device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c, double dx,
-                                            double dt, const double dsum[NF]) {
+// of one interior cell whose stage input is u; non-physical results are
+// reported in a.status.
+__device__ __forceinline__ void finish_cell_u(const StageArgs &a, int leaf, int c, double dx, double dt,
+                                              const double dsum[NF], const double u[NF]) {
     // leaf: the block; its cell c lives at base in U, fields fs apart
     const double idx = 1.0 / dx;
     const size_t base = block_base(leaf, a.ts, a.lg) + block_cell(c, a.lg);
     const size_t fs = (size_t)1 << (3 * a.lg);
-    double u[NF], L[NF];
+    double L[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        L[f] = -dsum[f] * idx;
-        u[f] = a.Uin[base + f * fs];
-    }
+    for (int f = 0; f < NF; ++f) L[f] = -dsum[f] * idx;
     // rotating-frame source -Omega x s
     L[SX] = L[SX] + a.ph.omega * u[SY];
     L[SY] = L[SY] - a.ph.omega * u[SX];
@@ -440,6 +438,17 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c,
         a.status->cell = (int)(base - ((size_t)lf * NF << (3 * a.lg)));   // index within the leaf
         a.status->field = badf;
     }
+}
+
+// The same, with the cell's stage input read from HBM.
+__device__ __forceinline__ void finish_cell(const StageArgs &a, int leaf, int c, double dx,
+                                            double dt, const double dsum[NF]) {
+    const size_t base = block_base(leaf, a.ts, a.lg) + block_cell(c, a.lg);
+    const size_t fs = (size_t)1 << (3 * a.lg);
+    double u[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u[f] = a.Uin[base + f * fs];
+    finish_cell_u(a, leaf, c, dx, dt, dsum, u);
 }
 
 // Time step of this launch: from device memory when the step is driven
@@ -757,18 +766,22 @@ __device__ __forceinline__ void col_axis_to_ws(int N, const StageArgs &a, const 
 }
 
 // The final pass of a leaf: sum the three axes' differences from W and
-// finish every interior cell.
+// finish every interior cell, whose stage input is still in the LDS block P
+// (only a few corner ghost cells may have been overwritten by then).
 __device__ __forceinline__ void col_finish_leaf(const StageArgs &a, int leaf, const double *W,
-                                                int tid, int nt) {
+                                                const double *P, int tid, int nt) {
     if (a.stage == 0) return;
     const double dx = a.dx[leaf >> a.ts];
     const double dt = stage_dt(a);
     for (int c = tid; c < NC; c += nt) {
-        double dsum[NF];
+        const int pc = pidx(c & 7, (c >> 3) & 7, c >> 6);
+        double dsum[NF], u[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
+        for (int f = 0; f < NF; ++f) {
             dsum[f] = (W[(0 * NF + f) * NC + c] + W[(1 * NF + f) * NC + c]) + W[(2 * NF + f) * NC + c];
-        finish_cell(a, leaf, c, dx, dt, dsum);
+            u[f] = P[f * NP + pc];
+        }
+        finish_cell_u(a, leaf, c, dx, dt, dsum, u);
     }
 }
 
@@ -818,7 +831,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col(StageArgs a) {
     double smax = 0.0;
     walk_columns<LEARNED>(a, P, leaf, W, 0, 3 * NX * NX, &next_task, tid, smax);
     __syncthreads();   // every slice of W is written
-    col_finish_leaf(a, leaf, W, tid, NTC);
+    col_finish_leaf(a, leaf, W, P, tid, NTC);
     block_max(smax, P, tid);
     if (tid == 0 && a.amax) store_amax(a, leaf, P, NTC / 64);
 }
@@ -878,7 +891,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
                      &next_task, tid, smax);
         if (T == 1) {
             __syncthreads();   // every slice of W is written
-            col_finish_leaf(a, leaf, W, tid, NTC);
+            col_finish_leaf(a, leaf, W, P, tid, NTC);
             block_max(smax, P, tid);
             if (tid == 0 && a.amax) store_amax(a, leaf, P, NTC / 64);
         } else {
@@ -897,7 +910,7 @@ __global__ void __launch_bounds__(NTC) stage_kernel_col_persistent(StageArgs a) 
             __syncthreads();
             if (last_s) {
                 __threadfence();   // see the other tiles' W
-                col_finish_leaf(a, leaf, W, tid, NTC);
+                col_finish_leaf(a, leaf, W, P, tid, NTC);
                 if (tid == 0 && a.amax) {
                     double *r = P;   // reuse: the three tile maxima
                     r[0] = a.tile_amax[(size_t)leaf * 3 + 0];
