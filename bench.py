@@ -551,6 +551,12 @@ def sedov_legs(torch, args):
                  "outflow, plain PPM, one launch per stage over all leaves")
     r = single_launch_leg(torch, args, w256, "sedov256", schedule="column")
     r.pop("U")
+    # the paper's own figure for this problem (section V-A2: 286 ms per
+    # three-stage step on 128 Summit nodes, 768 V100s, with 8^3 leaves);
+    # another machine's whole-code number, quoted for scale only
+    paper = 3 * 16777216 / 0.286
+    r["paper_context"] = {"value": paper, "unit": "cell-updates/s", "hardware": "128 Summit nodes (768 V100)",
+                          "ratio": r["value"] / paper}
     out["sedov256"] = r
     del w256
     wo = sedov_uniform(8)
