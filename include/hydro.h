@@ -320,12 +320,15 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
  * cells of each face-adjacent ghost slab x-, x+, y-, y+, z-, z+ by their two
  * in-block coordinates in axis order (slot 512 + 64 slab + u + 8 v) --
  * val (device [n T][7][26][896], [block][field][point][slot]; points numbered
- * as in hydro_reconstruct) receives the limited FP64 point values, and ok
+ * as in hydro_reconstruct) receives the limited FP64 point values, each the
+ * cell value plus a binary32 offset rounded toward zero (the stage itself
+ * keeps only the offsets: half the bytes), and ok
  * (device uint8 [n T][896]) 1 where the cell passes the FP64 check in all
  * seven fields, 0 where the stage takes plain PPM for it.  y (device float
  * [n T][7][896][26], may be NULL) receives the network's outputs of every row
  * whose neighbourhood is not flat (other rows may be left untouched).
- * Counts toward hydro_mlp_stats.  Asynchronous on g->stream. */
+ * With val and ok NULL the pre-pass writes the handle's own workspace, as in
+ * a stage.  Counts toward hydro_mlp_stats.  Asynchronous on g->stream. */
 int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, float *y);
 /* Cells reconstructed by the learned path and cells that fell back to plain
  * PPM since the previous call (synchronises). */

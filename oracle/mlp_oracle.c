@@ -8,7 +8,8 @@
  * is q_c + sigma * y_d in FP64.  A flat neighbourhood (sigma = 0) passes q_c
  * through exactly.  The plain limiter then acts on the predicted values
  * (clamp between the cell and each neighbour, PPM monotonicity constraint per
- * line), and every row is checked in FP64: each value must lie
+ * line; the results are kept as q_c plus a binary32 offset), and every row
+ * is checked in FP64 on those values: each value must lie
  * between the cell and its neighbour in that direction, each line's pair of
  * end values must satisfy the PPM monotonicity conditions, and rho, E, tau
  * must stay positive and X non-negative; a cell any of whose fields fails is
@@ -245,11 +246,27 @@ int oracle_mlp_row_ok(const double nb[27], const double val[26], int f)
     return 1;
 }
 
+/* Binary32 rounding toward zero: the nearest binary32 (the C conversion
+ * rounds to nearest), moved one unit toward zero where it came out larger in
+ * magnitude than x. */
+static float rz32(double x)
+{
+    float f = (float)x;
+    if (fabs((double)f) > fabs(x)) f = nextafterf(f, 0.0f);
+    return f;
+}
+
 /* The plain limiter applied to one row of predicted values: each value is
  * clamped between the cell and its neighbour in that direction, then each
  * line's pair goes through the PPM monotonicity constraint (flatten at an
- * extremum, else pull the far end in).  Values that already satisfy both are
- * left unchanged; a NaN stays NaN and fails the check afterwards. */
+ * extremum, else pull the far end in).  The limited values are kept as
+ * binary32 offsets from q_c, so the point value is q_c + offset: the offset
+ * of an end the constraint leaves is its difference from q_c rounded toward
+ * zero (toward the cell value, so a clamped end stays within its bounds);
+ * a pulled-in end, 3 q_c - 2 R, takes -2 times the other end's rounded
+ * offset, which keeps the pair on the constraint's boundary; a flattened
+ * pair has offsets zero.  Values that already satisfy both limits change
+ * only by that rounding; a NaN stays NaN and fails the check afterwards. */
 void oracle_mlp_limit(const double nb[27], double val[26])
 {
     double qc = nb[13];
@@ -266,16 +283,20 @@ void oracle_mlp_limit(const double nb[27], double val[26])
     for (int ln = 0; ln < 13; ++ln) {
         const int *d = LINES[ln];
         double *R = &val[d26(d[0], d[1], d[2])], *L = &val[d26(-d[0], -d[1], -d[2])];
-        if ((*R - qc) * (qc - *L) <= 0.0) {
-            *L = qc;
-            *R = qc;
-        } else {
+        float oR = 0.0f, oL = 0.0f;
+        if (!((*R - qc) * (qc - *L) <= 0.0)) {
+            int pullL = 0, pullR = 0;
             double D = *R - *L, M6 = 6.0 * (qc - 0.5 * (*L + *R));
             if (D * M6 > D * D)
-                *L = 3.0 * qc - 2.0 * *R;
+                pullL = 1;
             else if (D * M6 < -(D * D))
-                *R = 3.0 * qc - 2.0 * *L;
+                pullR = 1;
+            float fr = rz32(*R - qc), fl = rz32(*L - qc);
+            oR = pullR ? -2.0f * fl : fr;
+            oL = pullL ? -2.0f * fr : fl;
         }
+        *R = qc + (double)oR;
+        *L = qc + (double)oL;
     }
 }
 

@@ -50,7 +50,7 @@ struct hydro_t {
     int mlp_batch = 0;
     int adam_t = 0;
     bool mlp_loaded = false;
-    double *mlp_val = nullptr;     // [max_leaves][7][26][896]
+    float *mlp_off = nullptr;      // [max_leaves][7][26][896] point values as offsets
     uint8_t *mlp_ok = nullptr;     // [max_leaves][896]
     unsigned long long *fb_count = nullptr;
     int64_t mlp_cells = 0;
@@ -255,7 +255,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.leaf_done = h->leaf_done;
     a.tile_amax = h->tile_amax;
     a.grid_limit = h->num_cu;
-    a.mlp_val = nullptr;
+    a.mlp_off = nullptr;
     a.mlp_ok = nullptr;
     a.centre_only = h->p.scheme == 1;
     a.ts = h->ts;
@@ -300,7 +300,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.gmap = g->ghost_map;
             m.wbi = h->mt.wbi;
             m.bi = h->mt.bi;
-            m.val = h->mlp_val;
+            m.off = h->mlp_off;
             m.cell_ok = h->mlp_ok;
             m.fb_count = h->fb_count;
             m.leaf0 = a.leaf0;
@@ -311,7 +311,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, st);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
             h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
-            a.mlp_val = h->mlp_val;
+            a.mlp_off = h->mlp_off;
             a.mlp_ok = h->mlp_ok;
             if (a.kernel == KERNEL_FACE) a.kernel = KERNEL_COLUMN;   // the face walk has no learned variant
         }
@@ -476,7 +476,7 @@ hipError_t alloc_mlp(hydro_t *h, size_t nleaves) {
     if (e == hipSuccess) e = mlp_alloc(h, &t.gpart, (size_t)mlp::WG_SLICES * mlp::NPAR);
     if (e == hipSuccess) e = mlp_alloc(h, &h->fb_count, 1);
     if (e == hipSuccess && h->p.recon == 1) {
-        e = mlp_alloc(h, &h->mlp_val, nleaves * mlp::NSLOT * NF * 26);
+        e = mlp_alloc(h, &h->mlp_off, nleaves * mlp::NSLOT * NF * 26);
         if (e == hipSuccess) e = mlp_alloc(h, &h->mlp_ok, nleaves * mlp::NSLOT);
     }
     return e;
@@ -1008,7 +1008,7 @@ int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, 
     int rc = check_grid(h, g);
     if (rc) return rc;
     if (!g->U || !val != !ok) return fail(h, HYDRO_EINVAL, "null U, or only one of val and ok");
-    if (!val && !h->mlp_val) return fail(h, HYDRO_EINVAL, "val is NULL and the handle has no learned workspace");
+    if (!val && !h->mlp_off) return fail(h, HYDRO_EINVAL, "val is NULL and the handle has no learned workspace");
     if (!h->mlp_loaded) return fail(h, HYDRO_EINVAL, "hydro_mlp_load first");
     if ((rc = set_device(h))) return rc;
     mlp::MlpInfer m{};
@@ -1016,7 +1016,8 @@ int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, 
     m.gmap = g->ghost_map;
     m.wbi = h->mt.wbi;
     m.bi = h->mt.bi;
-    m.val = val ? val : h->mlp_val;
+    m.val = val;
+    m.off = val ? nullptr : h->mlp_off;
     m.cell_ok = ok ? ok : h->mlp_ok;
     m.fb_count = h->fb_count;
     m.leaf0 = 0;

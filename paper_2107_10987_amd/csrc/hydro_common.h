@@ -63,7 +63,8 @@ struct StageArgs {
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
     // learned reconstruction (null: plain PPM)
-    const double *mlp_val;    // [n][7][26][896] learned point values (field, dir, slot)
+    const float *mlp_off;     // [n][7][26][896] learned point values as binary32 offsets
+                              // from the cell value (field, dir, slot)
     const uint8_t *mlp_ok;    // [n][896]
     // flux correction at coarse/fine faces (null: none)
     const int32_t *face_flags;  // [n]: bits 0-5 corrected faces, 8-13 faces kept for a coarser leaf

@@ -38,23 +38,37 @@ __host__ __device__ inline int slot_of(int i, int j, int k) {
     return 512 + 64 * (k < 0 ? 4 : 5) + i + 8 * j;
 }
 
+// Binary32 rounding toward zero of x: the nearest binary32, stepped one unit
+// toward zero where it came out larger in magnitude (sign-magnitude bits:
+// one less in the integer view is one unit smaller in magnitude).
+__device__ __forceinline__ float rz32(double x) {
+    float f = (float)x;
+    if (fabs((double)f) > fabs(x)) f = __int_as_float(__float_as_int(f) - 1);
+    return f;
+}
+
 // The plain limiter on a predicted pair of one line (R at +d, L at -d), the
 // cell value qc and its neighbours nbR (at +d) and nbL (at -d): each value
 // clamped between the cell and its neighbour in that direction, then the PPM
-// monotonicity constraint on the pair (unfused FP64).  min/max clamps carry a
-// NaN prediction to a bound; the pre-pass's check fails it.
-__device__ __forceinline__ void learned_limit(double qc, double nbR, double nbL, double &R, double &L) {
+// monotonicity constraint on the pair (unfused FP64).  The results are kept
+// as binary32 offsets from qc (the point value is qc + offset in FP64),
+// rounded toward zero, i.e. toward the cell value, so a clamped end stays
+// between the cell and its neighbour; an end the constraint pulls in
+// (3 qc - 2 R, offset -2 (R - qc)) takes -2 times the other end's rounded
+// offset (exact), so the pair stays on the constraint's boundary.  min/max
+// clamps carry a NaN prediction to a bound; the pre-pass's check fails it.
+__device__ __forceinline__ void learned_limit(double qc, double nbR, double nbL, double R, double L, float &oR,
+                                              float &oL) {
     const double loR = fmin(qc, nbR), hiR = fmax(qc, nbR);
     const double loL = fmin(qc, nbL), hiL = fmax(qc, nbL);
-    double r = fmin(fmax(R, loR), hiR), l = fmin(fmax(L, loL), hiL);
+    const double r = fmin(fmax(R, loR), hiR), l = fmin(fmax(L, loL), hiL);
     const bool ext = (r - qc) * (qc - l) <= 0.0;
     const double D = r - l, M6 = 6.0 * (qc - 0.5 * (l + r));
     const double DM = D * M6, DD = D * D;
     const bool lowL = DM > DD, lowR = !lowL & (DM < -DD);
-    const double ln = lowL ? 3.0 * qc - 2.0 * r : l;
-    const double rn = lowR ? 3.0 * qc - 2.0 * l : r;
-    L = ext ? qc : ln;
-    R = ext ? qc : rn;
+    const float fr = rz32(r - qc), fl = rz32(l - qc);
+    oR = ext ? 0.0f : (lowR ? -2.0f * fl : fr);
+    oL = ext ? 0.0f : (lowL ? -2.0f * fr : fl);
 }
 
 struct MlpTrain {
@@ -74,7 +88,9 @@ struct MlpInfer {
     const int32_t *gmap;        // [blocks][2232]
     const uint16_t *wbi;        // bf16 inference image
     const float *bi;            // its float32 biases
-    double *val;                // [blocks][7][26][896] limited point values (field, dir, slot)
+    float *off;                 // [blocks][7][26][896] point values as offsets from the cell
+                                // value (field, dir, slot), or null
+    double *val;                // the same as FP64 point values, or null
     uint8_t *cell_ok;           // [blocks][896]
     unsigned long long *fb_count;  // cells that fell back to plain PPM
     int leaf0;                  // first block of the launch

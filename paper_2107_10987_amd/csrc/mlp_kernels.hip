@@ -416,20 +416,22 @@ __device__ __forceinline__ v8bf infer_frag(const uint16_t *W, int F, int lane) {
 // The plain limiter and the FP64 check on one line of a row, on its two
 // predicted values R (at +d) and L (at -d): each value clamped between the
 // cell and its neighbour in that direction, the pair put through the PPM
-// monotonicity constraint, then checked (bounds, positivity of rho, E, tau,
-// non-negative X, the monotonicity conditions with a rounding slack of
-// 1e-13 |D| (|L| + |q| + |R|)).  Limiter and check only ever couple the two
-// ends of one line, so a row is processed line by line.  nbR / nbL are the
-// neighbours in those directions.  Returns whether the line passes.  Written
-// without branches: min/max clamps (a NaN prediction, which they would turn
-// into a bound, fails explicitly) and selects for the constraint's cases.
-__device__ __forceinline__ bool limit_check_line(double qc, double nbR, double nbL, int f, double &R,
-                                                 double &L) {
+// monotonicity constraint and kept as binary32 offsets oR, oL from qc (see
+// learned_limit), then the point values qc + offset are checked in FP64
+// (bounds, positivity of rho, E, tau, non-negative X, the monotonicity
+// conditions with a rounding slack of 1e-13 |D| (|L| + |q| + |R|)).  Limiter
+// and check only ever couple the two ends of one line, so a row is processed
+// line by line.  nbR / nbL are the neighbours in those directions.  Returns
+// whether the line passes.  Written without branches: min/max clamps (a NaN
+// prediction, which they would turn into a bound, fails explicitly) and
+// selects for the constraint's cases.
+__device__ __forceinline__ bool limit_check_line(double qc, double nbR, double nbL, int f, double R, double L,
+                                                 float &oR, float &oL) {
     bool ok = (R == R) & (L == L);
     const double loR = fmin(qc, nbR), hiR = fmax(qc, nbR);
     const double loL = fmin(qc, nbL), hiL = fmax(qc, nbL);
-    double r = R, l = L;
-    learned_limit(qc, nbR, nbL, r, l);
+    learned_limit(qc, nbR, nbL, R, L, oR, oL);
+    const double r = qc + (double)oR, l = qc + (double)oL;
     ok = ok & (r >= loR) & (r <= hiR) & (l >= loL) & (l <= hiL);
     if (f == RHO || f == EGAS || f == TAU) ok = ok & (r > 0.0) & (l > 0.0);
     if (f == SPC) ok = ok & (r >= 0.0) & (l >= 0.0);
@@ -439,8 +441,6 @@ __device__ __forceinline__ bool limit_check_line(double qc, double nbR, double n
         const bool mono = ((r - qc) * (qc - l) > 0.0) & !(DM > lim) & !(DM < -lim);
         ok = ok & (((l == qc) & (r == qc)) | mono);
     }
-    R = r;
-    L = l;
     return ok;
 }
 
@@ -460,6 +460,9 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 // over the group by lane exchange), the three layers on MFMA, and the limiter
 // and FP64 check for its lines.  Point values go out as val[block][field]
 // [dir][slot]; a cell passes when all seven of its rows pass.
+// VAL64: the point values go out in FP64 to m.val (inspection), else as the
+// binary32 offsets the stage reads to m.off.
+template <bool VAL64>
 __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7))) mlp_infer_kernel(MlpInfer m) {
     __shared__ double box[NF][BOX];                               // 16,800 B
     __shared__ __attribute__((aligned(16))) uint16_t W[WBI_SIZE];  // 16,384 B
@@ -522,7 +525,8 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
     }
     __syncthreads();
     const double *bx = box[f];
-    double *vout = m.val + ((size_t)blk * NF + f) * 26 * NSLOT;
+    float *oout = VAL64 ? nullptr : m.off + ((size_t)blk * NF + f) * 26 * NSLOT;
+    double *vout = VAL64 ? m.val + ((size_t)blk * NF + f) * 26 * NSLOT : nullptr;
     unsigned long long wfail = 0;
 #pragma unroll 1
     for (int tt = 0; tt < 4; ++tt) {
@@ -556,8 +560,13 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (4 * q + t >= 13) continue;
-                vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc;
-                vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc;
+                if (VAL64) {
+                    vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc;
+                    vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc;
+                } else {
+                    oout[(size_t)(lrow[t] & 255) * NSLOT + slot] = 0.0f;
+                    oout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = 0.0f;
+                }
             }
             continue;
         }
@@ -628,14 +637,19 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
                 yr[lrow[t] & 255] = y[0][t];
                 yr[lrow[t] >> 8] = y[1][t];
             }
-            double R = qc, L = qc;
+            float oR = 0.0f, oL = 0.0f;
             if (!flat) {
-                R = qc + sig * (double)y[0][t];
-                L = qc + sig * (double)y[1][t];
-                ok = limit_check_line(qc, bx[cb + loff[t]], bx[cb - loff[t]], f, R, L) && ok;
+                const double R = qc + sig * (double)y[0][t];
+                const double L = qc + sig * (double)y[1][t];
+                ok = limit_check_line(qc, bx[cb + loff[t]], bx[cb - loff[t]], f, R, L, oR, oL) && ok;
             }
-            vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = R;
-            vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = L;
+            if (VAL64) {
+                vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc + (double)oR;
+                vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc + (double)oL;
+            } else {
+                oout[(size_t)(lrow[t] & 255) * NSLOT + slot] = oR;
+                oout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = oL;
+            }
         }
         const unsigned long long bad = __ballot(!ok);
         wfail |= ((bad | (bad >> 16) | (bad >> 32) | (bad >> 48)) & 0xffffull) << (16 * tt);
@@ -659,7 +673,10 @@ hipError_t hydro_mlp_upload_pad_ghost(const int16_t *pad_ghost) {
 
 hipError_t hydro_mlp_launch_infer(const MlpInfer &m, int nleaf, hipStream_t s) {
     if (nleaf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3(nleaf * ICHUNK), dim3(64 * NF), 0, s, m);
+    if (m.val)
+        hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(nleaf * ICHUNK), dim3(64 * NF), 0, s, m);
+    else
+        hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(nleaf * ICHUNK), dim3(64 * NF), 0, s, m);
     return hipGetLastError();
 }
 

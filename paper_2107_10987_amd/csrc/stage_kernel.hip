@@ -587,8 +587,8 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
 // Where a lane's point values come from: plain PPM, or (learned
 // reconstruction, cell passed the FP64 check) the inference pre-pass.
 struct ValSrc {
-    const double *val;     // this cell's values, (field f, dir d) at val[(26 f + d) * 896],
-                           // or null for plain PPM
+    const float *off;      // this cell's values as offsets from its own value, (field f,
+                           // dir d) at off[(26 f + d) * 896], or null for plain PPM
 };
 
 __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
@@ -599,15 +599,54 @@ __device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
 template <bool LEARNED>
 __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy, int dz,
                                           const ValSrc &src, double pos[NF], double neg[NF]) {
-    if (LEARNED && src.val) {
+    if (LEARNED && src.off) {
         const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
+        float op[NF], om[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            pos[f] = src.val[(size_t)(f * 26 + dp) * mlp::NSLOT];
-            neg[f] = src.val[(size_t)(f * 26 + dm) * mlp::NSLOT];
+            op[f] = src.off[(size_t)(f * 26 + dp) * mlp::NSLOT];
+            om[f] = src.off[(size_t)(f * 26 + dm) * mlp::NSLOT];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double qc = P[f * NP + c];
+            pos[f] = qc + (double)op[f];
+            neg[f] = qc + (double)om[f];
         }
     } else {
         line_ends(P, c, dx, dy, dz, pos, neg);
+    }
+}
+
+// Both lines of a pair, d1 and d2: with learned values, every offset of the
+// pair is loaded before any is used, so the loads of the two lines are in
+// flight together.
+template <bool LEARNED>
+__device__ __forceinline__ void pair_vals(const double *P, int c, int x1, int y1, int z1, int x2, int y2, int z2,
+                                          const ValSrc &src, double pos1[NF], double neg1[NF], double pos2[NF],
+                                          double neg2[NF]) {
+    if (LEARNED && src.off) {
+        const int p1 = dir26_of(x1, y1, z1), m1 = dir26_of(-x1, -y1, -z1);
+        const int p2 = dir26_of(x2, y2, z2), m2 = dir26_of(-x2, -y2, -z2);
+        float o[4][NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            o[0][f] = src.off[(size_t)(f * 26 + p1) * mlp::NSLOT];
+            o[1][f] = src.off[(size_t)(f * 26 + m1) * mlp::NSLOT];
+            o[2][f] = src.off[(size_t)(f * 26 + p2) * mlp::NSLOT];
+            o[3][f] = src.off[(size_t)(f * 26 + m2) * mlp::NSLOT];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double qc = P[f * NP + c];
+            pos1[f] = qc + (double)o[0][f];
+            neg1[f] = qc + (double)o[1][f];
+            pos2[f] = qc + (double)o[2][f];
+            neg2[f] = qc + (double)o[3][f];
+        }
+    } else {
+        line_ends(P, c, x1, y1, z1, pos1, neg1);
+        line_ends(P, c, x2, y2, z2, pos2, neg2);
     }
 }
 
@@ -663,10 +702,10 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     const int bk = (N == 2) ? cell : c2;
     const int cB = pidx(bi, bj, bk);
     ValSrc src{nullptr};
-    if (LEARNED && a.mlp_val) {
+    if (LEARNED && a.mlp_off) {
         const int slot = mlp::slot_of(bi, bj, bk);
         if (a.mlp_ok[(size_t)leaf * mlp::NSLOT + slot])
-            src.val = a.mlp_val + (size_t)leaf * NF * 26 * mlp::NSLOT + slot;
+            src.off = a.mlp_off + (size_t)leaf * NF * 26 * mlp::NSLOT + slot;
     }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;
@@ -701,8 +740,8 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
         const int tb = (p == 0) ? 0 : ((p == 3) ? -1 : 1);
         const double w = (p < 2) ? 4.0 / 36.0 : 1.0 / 36.0;
         double pos1[NF], neg1[NF], pos2[NF], neg2[NF];
-        line_vals<LEARNED>(P, cB, dirx(ta, tb), diry(ta, tb), dirz(ta, tb), src, pos1, neg1);
-        line_vals<LEARNED>(P, cB, dirx(-ta, -tb), diry(-ta, -tb), dirz(-ta, -tb), src, pos2, neg2);
+        pair_vals<LEARNED>(P, cB, dirx(ta, tb), diry(ta, tb), dirz(ta, tb), dirx(-ta, -tb), diry(-ta, -tb),
+                           dirz(-ta, -tb), src, pos1, neg1, pos2, neg2);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             pos1[f] = shfl_up1(pos1[f]);
@@ -1038,7 +1077,7 @@ hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(stage_kernel, dim3(a.nleaf), dim3(NT), 0, s, a);
         break;
     case KERNEL_COLUMN:
-        if (a.mlp_val)
+        if (a.mlp_off)
             hipLaunchKernelGGL(stage_kernel_col<true>, dim3(a.nleaf), dim3(NTC), 0, s, a);
         else
             hipLaunchKernelGGL(stage_kernel_col<false>, dim3(a.nleaf), dim3(NTC), 0, s, a);
@@ -1046,7 +1085,7 @@ hipError_t hydro_launch_stage(const StageArgs &a, hipStream_t s) {
     default: {   // persistent column walk
         const int items = a.nleaf * a.tiles;
         const int grid = items < a.grid_limit ? items : a.grid_limit;
-        if (a.mlp_val)
+        if (a.mlp_off)
             hipLaunchKernelGGL(stage_kernel_col_persistent<true>, dim3(grid), dim3(NTC), 0, s, a);
         else
             hipLaunchKernelGGL(stage_kernel_col_persistent<false>, dim3(grid), dim3(NTC), 0, s, a);

@@ -19,7 +19,8 @@ Two kinds of network:
   moves an output by about |W3| 2^-8 |a|.  Raw outputs are compared element by
   element against a bound derived from that; point values within
   2 sigma max|dy| of the row (the limiter's clamp is 1-Lipschitz, the
-  constraint 3 q_c - 2 R at most 2-Lipschitz), except lines that one side
+  constraint 3 q_c - 2 R at most 2-Lipschitz) plus the binary32 rounding
+  of offsets from q_c of at most 2 sigma on each side, except lines that one side
   flattens at an extremum while the other has an end within that distance of
   q_c (the constraint's only discontinuity); cell verdicts may differ only on
   a small counted set of cells.
@@ -290,7 +291,8 @@ def _compare_tolerant(case, params, val, ok, y):
         s = sig[sc][both]
         q = qc[sc][both]
         dmax = dy_row[both]
-        bound = 2.0 * s * dmax + 8.0 * np.spacing(np.maximum(np.abs(q), s))   # [m][7]
+        # (+ the two sides' binary32 roundings of offsets up to 2 sigma)
+        bound = 2.0 * s * dmax + 2.0 ** -20 * s + 8.0 * np.spacing(np.maximum(np.abs(q), s))   # [m][7]
         err = np.abs(g - o)
         bad = err > bound[..., None]
         if bad.any():

@@ -127,8 +127,16 @@ def test_limiter_makes_predictions_pass_and_keeps_valid_rows(oracle_mod):
             nb, s, x = oracle_mod.mlp_features(P, i, j, k, f)
             if x is None:
                 continue
-            # valid values (plain PPM) pass through the limiter unchanged
-            assert np.array_equal(oracle_mod.mlp_limit(nb, V[c, :, f]), V[c, :, f])
+            # valid values (plain PPM) pass through the limiter changed only
+            # by keeping their offsets from q_c in binary32 (a pair on the
+            # constraint's boundary may be re-pulled: twice the other end's
+            # rounding), and still pass the check
+            v = V[c, :, f]
+            lim = oracle_mod.mlp_limit(nb, v)
+            qc = nb[13]
+            tol = 2.0 ** -21 * np.abs(v - qc) + 8 * np.spacing(np.maximum(abs(qc), np.abs(v)))
+            assert np.all(np.abs(lim - v) <= tol)
+            assert oracle_mod.mlp_row_ok(nb, lim, f)
             # noisy predictions are limited into values that pass the check
             noisy = V[c, :, f] + 0.3 * s * rng.normal(size=26)
             lim = oracle_mod.mlp_limit(nb, noisy)
@@ -211,3 +219,48 @@ def test_rows_are_the_table_before_fallback(oracle_mod):
     needed = [c for c in range(1000)
               if sum(v < 0 or v > 7 for v in (c % 10 - 1, (c // 10) % 10 - 1, c // 100 - 1)) <= 1]
     assert nf == sum(not ok[c].all() for c in needed)
+
+
+def _rz_ok(o, x):
+    """o is binary32, no larger in magnitude than x, of x's sign (or zero),
+    and the next binary32 away from zero is larger in magnitude than x: the
+    rounding of x toward zero."""
+    f = np.float32(o)
+    if float(f) != o or abs(o) > abs(x) or (o != 0 and np.sign(o) != np.sign(x)):
+        return False
+    up = np.nextafter(f, np.float32(np.copysign(np.inf, x)), dtype=np.float32)
+    return abs(float(up)) > abs(x)
+
+
+def test_limiter_keeps_binary32_offsets_toward_the_cell(oracle_mod):
+    """One row with q_c = 0, so the point values are the offsets themselves:
+    every neighbour is 0 except the +x one (1) and the -x one (-1), so only
+    the x line is not flattened by its bounds."""
+    nb = np.zeros(27)
+    nb[14], nb[12] = 1.0, -1.0                       # (+1, 0, 0) and (-1, 0, 0)
+    xp, xm = 13, 12  # d26 of (+1,0,0) and (-1,0,0)
+    val = np.full(26, 0.05)
+    # no constraint: (R - q)(q - L) > 0 and |M6| < |D|
+    R, L = 0.3 + 1e-12, -0.2 - 1e-12
+    val[xp], val[xm] = R, L
+    lim = oracle_mod.mlp_limit(nb, val)
+    assert _rz_ok(lim[xp], R) and _rz_ok(lim[xm], L)
+    others = [d for d in range(26) if d not in (xp, xm)]
+    assert np.all(lim[others] == 0.0)                 # clamped to [0, 0]
+    # R far out: the constraint pulls R in to 3 q_c - 2 L, kept as -2 x
+    # the rounded offset of L, exactly
+    val[xp], val[xm] = 0.9, -0.1 - 1e-12
+    lim = oracle_mod.mlp_limit(nb, val)
+    assert _rz_ok(lim[xm], val[xm]) and lim[xp] == -2.0 * lim[xm]
+    # and L far out: L becomes -2 x the rounded offset of R
+    val[xp], val[xm] = 0.1 + 1e-12, -0.9
+    lim = oracle_mod.mlp_limit(nb, val)
+    assert _rz_ok(lim[xp], val[xp]) and lim[xm] == -2.0 * lim[xp]
+    # an extremum flattens both ends to q_c
+    val[xp], val[xm] = 0.3, 0.2
+    lim = oracle_mod.mlp_limit(nb, val)
+    assert lim[xp] == 0.0 and lim[xm] == 0.0
+    # a NaN prediction stays NaN (and fails the check)
+    val[xp], val[xm] = np.nan, -0.2
+    lim = oracle_mod.mlp_limit(nb, val)
+    assert np.isnan(lim[xp]) and not oracle_mod.mlp_row_ok(nb, lim, 1)
