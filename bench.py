@@ -59,9 +59,10 @@ FLOPS_PER_CELL_UPDATE_OLD = 1692.0
 # the step-start state in the second stage (+56 B, half of it per stage).
 BYTES_PER_CELL_UPDATE = 140.0
 # The learned reconstruction's network: 2 (34*64 + 64*64 + 64*26) flops per
-# row, 7 rows per cell, 896 needed cells per 8^3 block.
+# row, 7 rows per cell; an 8^3 block needs the rows of 896 cells, 512 of its
+# own and 384 face-adjacent ghost cells (evaluated unless another block's
+# pre-pass holds them).
 MLP_FLOPS_PER_ROW = 2.0 * (34 * 64 + 64 * 64 + 64 * 26)
-MLP_FLOPS_PER_BLOCK = MLP_FLOPS_PER_ROW * 7 * 896
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
@@ -141,10 +142,24 @@ def fp64_roofline(kernel: str, cells: int, seconds: float, traffic=None, flops=F
             "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic}
 
 
-def mfma_roofline(blocks: int, seconds: float, traffic=None):
-    ach = MLP_FLOPS_PER_BLOCK * blocks / seconds / 1e12
+def prepass_cells(g) -> int:
+    """Cells whose rows one pre-pass over all of g's blocks evaluates: every
+    block's 512 interior cells and the 64 of each ghost slab not wholly shared
+    with other blocks (hydro_mlp_alias_map; every block is in the one launch)."""
+    blocks = g.gmap.numel() // 2232
+    if g.alias is None:
+        return blocks * 896
+    shared = (g.alias.reshape(blocks, 6, 64) >= 0).all(dim=2)
+    return int(blocks * 896 - 64 * int(shared.sum()))
+
+
+def mfma_roofline(cells: int, seconds: float, traffic=None):
+    """bf16-MFMA fraction of the pre-pass: the network's flops over the rows
+    it evaluates (7 per cell)."""
+    ach = MLP_FLOPS_PER_ROW * 7 * cells / seconds / 1e12
     return {"kernel": "mlp_infer_kernel", "bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS,
-            "unit": "TFLOP/s", "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic}
+            "unit": "TFLOP/s", "frac": ach / PEAK_BF16_TFLOPS, "traffic": traffic,
+            "rows_per_launch": 7 * cells}
 
 
 def hbm_figures(cells: int, seconds: float, traffic=None):
@@ -429,7 +444,7 @@ def single_launch_leg(torch, args, w, name, params=None, schedule=None, centre_o
             blocks = w.n * (w.tree.leaf_edge // 8) ** 3
             ptraffic = measured_traffic(tname, "mlp_infer_kernel")
             out["prepass"] = {"seconds": tp, "us_per_block": tp / blocks * 1e6,
-                              "roofline": mfma_roofline(blocks, tp, ptraffic),
+                              "roofline": mfma_roofline(prepass_cells(g), tp, ptraffic),
                               "hbm_bytes_per_cell_update": (None if ptraffic is None else ptraffic / w.cells)}
         out["U"] = g.U.cpu().numpy()
         return out
@@ -512,7 +527,7 @@ def polytrope_legs(torch, args, params):
                 tp = time_prepass(torch, hy, g, torch.cuda.current_stream())
                 ptraffic = measured_traffic(tname, "mlp_infer_kernel")
                 out[name]["prepass"] = {"seconds": tp, "us_per_block": tp / w.n * 1e6,
-                                        "roofline": mfma_roofline(w.n, tp, ptraffic),
+                                        "roofline": mfma_roofline(prepass_cells(g), tp, ptraffic),
                                         "hbm_bytes_per_cell_update": (None if ptraffic is None
                                                                       else ptraffic / w.cells)}
         finally:

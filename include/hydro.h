@@ -103,6 +103,7 @@ typedef struct hydro_grid {
     int32_t n_reflux;          /*   entries in the list (may be 0)                   */
     const int32_t *prolong;    /* device [n_prolong][8] from hydro_ghost_map_linear  */
     int32_t n_prolong;         /*   (NULL, 0 with a plain ghost map)                 */
+    const int32_t *mlp_alias;  /* device [n T][384] from hydro_mlp_alias_map, or NULL */
 } hydro_grid;
 
 /* Octree description used to build the ghost map (host memory). */
@@ -314,6 +315,21 @@ int hydro_mlp_train_step(hydro_t *h, const float *X, const float *T, int B, doub
  * plain PPM point values in the same normalisation T (device [n*3584][26]),
  * valid (device [n*3584], 0 where the neighbourhood is flat).  8^3 leaves only. */
 int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t *valid);
+/* Rows of the learned reconstruction that two blocks share, for the learned
+ * stages of a grid (host memory, built from the tree and its host ghost map,
+ * plain or linear).  A face-adjacent ghost cell of block b that copies cell X
+ * of block b2 (same level, or the periodic image) gets, when the 3x3x3
+ * neighbourhoods of the two cells are filled from the same sources in every
+ * cell, the entry b2 * 896 + slot of X (its network inputs, outputs and
+ * verdict are then those of X, bit for bit); else -1.  alias[n T][384] in
+ * slot order 512..895 of hydro_mlp_values.  Pass it (on the device) as
+ * hydro_grid.mlp_alias: a learned stage's pre-pass then skips every ghost slab
+ * all of whose cells alias blocks of the same launch, and the stage reads
+ * those cells' values from the aliased rows.  HYDRO_EINVAL for a bad tree.
+ * Synchronous; needs no handle and no GPU.  Not in the paper: the learned
+ * reconstruction is an extension. */
+int hydro_mlp_alias_map(const hydro_tree *t, const int32_t *map, int32_t *alias);
+
 /* The learned reconstruction's pre-pass of a stage alone, for the state g->U
  * (test and inspection support).  For every 8^3 block b (T per leaf) and every
  * cell slot s its fluxes need -- the 512 interior cells by index, then the 64
@@ -327,11 +343,15 @@ int hydro_mlp_pairs(hydro_t *h, const hydro_grid *g, float *X, float *T, uint8_t
  * seven fields, 0 where the stage takes plain PPM for it.  y (device float
  * [n T][7][896][26], may be NULL) receives the network's outputs of every row
  * whose neighbourhood is not flat (other rows may be left untouched).
- * With val and ok NULL the pre-pass writes the handle's own workspace, as in
- * a stage.  Counts toward hydro_mlp_stats.  Asynchronous on g->stream. */
+ * With val and ok NULL the pre-pass writes the handle's own workspace exactly
+ * as in a stage (skipping the ghost slabs g->mlp_alias shares); with val
+ * every slot is computed.  Counts toward hydro_mlp_stats.  Asynchronous on
+ * g->stream. */
 int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, float *y);
 /* Cells reconstructed by the learned path and cells that fell back to plain
- * PPM since the previous call (synchronises). */
+ * PPM since the previous call (synchronises): each block's interior cells,
+ * 512 per block and pre-pass (a face-adjacent ghost cell is counted in the
+ * block it belongs to). */
 int hydro_mlp_stats(hydro_t *h, int64_t *cells, int64_t *fallback);
 
 /* Device pointer to the maximum signal speeds of the last step, one per 8^3

@@ -229,7 +229,8 @@ class Oracle:
 
     def stage_learned(self, params, stage: int, dt: float, Uin, Un=None, l0=0, l1=None):
         """One stage with the learned reconstruction (plain-PPM fallback per
-        cell); returns (Uout, amax, fallback cells per leaf) for [l0, l1)."""
+        cell); returns (Uout, amax, interior cells per leaf that fell back)
+        for [l0, l1)."""
         par = np.ascontiguousarray(params, dtype=np.float32)
         Uin = _f64(Uin)
         Un = Uin if Un is None else _f64(Un)
@@ -359,7 +360,7 @@ def mlp_limit(nb, vals):
 
 def learned_values(P, params):
     """Learned point-value table [1000][26][7] of one padded block, with the
-    count of needed cells and of those that fell back to plain PPM."""
+    count of its interior cells and of those that fell back to plain PPM."""
     P = _f64(P)
     par = np.ascontiguousarray(params, dtype=np.float32)
     V = np.zeros((1000, 26, NF))

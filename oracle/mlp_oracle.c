@@ -336,10 +336,10 @@ void oracle_learned_rows(const double *P, const float *par, double *y, double *v
 }
 
 /* Point-value table (oracle_reconstruct_values layout) of one padded block
- * by the learned reconstruction with plain-PPM fallback.  Cells needed by the
- * fluxes are the interior and the face-adjacent ghost cells; *needed and
- * *fallback count those cells and the ones that fell back.  Every cell -1..8
- * gets values so the table is complete. */
+ * by the learned reconstruction with plain-PPM fallback.  The fluxes need the
+ * interior and the face-adjacent ghost cells; *needed and *fallback count the
+ * interior cells and those of them that fell back (a ghost cell is counted in
+ * its own block).  Every cell -1..8 gets values so the table is complete. */
 void oracle_learned_values(const double *P, const float *par, double *V, int *needed, int *fallback)
 {
     const long ncell = (long)RBC * RBC * RBC;
@@ -357,7 +357,7 @@ void oracle_learned_values(const double *P, const float *par, double *V, int *ne
                 const long c = rix(i, j, k);
                 int cell_ok = 1;
                 for (int f = 0; f < NFC; ++f) cell_ok &= ok[c * NFC + f];
-                if (outside <= 1) {
+                if (outside == 0) {
                     ++nn;
                     nf += !cell_ok;
                 }
@@ -375,7 +375,8 @@ void oracle_learned_values(const double *P, const float *par, double *V, int *ne
 }
 
 /* One SSP-RK2 stage of leaves [l0, l1) with the learned reconstruction;
- * otherwise as oracle_stage.  fallback[l] counts leaf l's fallback cells. */
+ * otherwise as oracle_stage.  fallback[l] counts leaf l's interior cells that
+ * fell back. */
 static int learned_values(const double *P, void *ctx, double *V)
 {
     int nn, nf;

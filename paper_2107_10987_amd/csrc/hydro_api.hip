@@ -257,6 +257,7 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.grid_limit = h->num_cu;
     a.mlp_off = nullptr;
     a.mlp_ok = nullptr;
+    a.mlp_alias = nullptr;
     a.centre_only = h->p.scheme == 1;
     a.ts = h->ts;
     a.lg = h->lg;
@@ -308,11 +309,13 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
             m.lg = h->lg;
             m.prolong = g->prolong;
             m.n_prolong = g->n_prolong;
+            m.alias = g->mlp_alias;
             hipError_t e = hydro_mlp_launch_infer(m, a.nleaf, st);
             if (e != hipSuccess) return hip_fail(h, e, "inference launch");
-            h->mlp_cells += (int64_t)a.nleaf * mlp::NSLOT;
+            h->mlp_cells += (int64_t)a.nleaf * NC;
             a.mlp_off = h->mlp_off;
             a.mlp_ok = h->mlp_ok;
+            a.mlp_alias = g->mlp_alias;
             if (a.kernel == KERNEL_FACE) a.kernel = KERNEL_COLUMN;   // the face walk has no learned variant
         }
         const bool rec = allow_timing && h->timing && 2 * (h->ev_used + 1) <= h->ev.size();
@@ -1018,6 +1021,7 @@ int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, 
     m.bi = h->mt.bi;
     m.val = val;
     m.off = val ? nullptr : h->mlp_off;
+    m.alias = val ? nullptr : g->mlp_alias;   // into the workspace: exactly a stage's pre-pass
     m.cell_ok = ok ? ok : h->mlp_ok;
     m.fb_count = h->fb_count;
     m.leaf0 = 0;
@@ -1029,7 +1033,7 @@ int hydro_mlp_values(hydro_t *h, const hydro_grid *g, double *val, uint8_t *ok, 
     const int nblk = g->n << h->ts;
     hipError_t e = hydro_mlp_launch_infer(m, nblk, (hipStream_t)g->stream);
     if (e != hipSuccess) return hip_fail(h, e, "inference launch");
-    h->mlp_cells += (int64_t)nblk * mlp::NSLOT;
+    h->mlp_cells += (int64_t)nblk * NC;
     return HYDRO_OK;
 }
 
@@ -1112,6 +1116,54 @@ int hydro_ghost_map_linear(const hydro_tree *t, int32_t *map, int32_t *table, in
     if (!n_table) return fail(nullptr, HYDRO_EINVAL, "null n_table");
     if (capacity < 0) return fail(nullptr, HYDRO_EINVAL, "capacity < 0");
     return build_ghost_map(t, map, table, capacity, n_table);
+}
+
+int hydro_mlp_alias_map(const hydro_tree *t, const int32_t *map, int32_t *alias) {
+    if (!map || !alias) return fail(nullptr, HYDRO_EINVAL, "null map or alias");
+    TreeIndex ti;
+    int rc = ti.build(t);   // validates the tree (levels, coordinates, leaf edge)
+    if (rc) return rc;
+    const int lg = t->leaf_edge == 16 ? 4 : 3;
+    const int64_t E = (int64_t)1 << lg, cells = E * E * E;
+    const int tiles = t->leaf_edge == 16 ? 8 : 1;
+    const int64_t nblk = (int64_t)t->n * tiles;
+    const std::vector<int16_t> pg = pad_ghost_table();
+    // what fills padded cell (i, j, k) of block b: the global index of an
+    // interior cell, or the block's ghost-map entry (a copy, a mean or a
+    // prolongation row); equal descriptors mean equal values in any state
+    auto desc = [&](int64_t b, int i, int j, int k) -> int64_t {
+        if (i >= 0 && i < NX && j >= 0 && j < NX && k >= 0 && k < NX) {
+            const int tile = (int)(b % tiles);
+            const int64_t x = 8 * (tile & 1) + i, y = 8 * ((tile >> 1) & 1) + j, z = 8 * (tile >> 2) + k;
+            return (b / tiles) * cells + (z * E + y) * E + x;
+        }
+        return map[b * NG + pg[((k + GW) * PB + (j + GW)) * PB + (i + GW)]];
+    };
+    constexpr int NGS = mlp::NSLOT - NC;   // 384 face-adjacent ghost cells
+    for (int64_t b = 0; b < nblk; ++b) {
+        for (int s = 0; s < NGS; ++s) {
+            const int slab = s / 64, u = s % 8, v = (s / 8) % 8, side = slab & 1;
+            const int e = side ? NX : -1;
+            const int i = slab < 2 ? e : u, j = slab < 2 ? u : (slab < 4 ? e : v), k = slab < 4 ? v : e;
+            int32_t out = -1;
+            const int64_t src = desc(b, i, j, k);
+            if (src >= 0 && src < (int64_t)t->n * cells) {
+                // the copied cell X: interior cell (ci, cj, ck) of block b2
+                const int64_t loc = src % cells;
+                const int x = (int)(loc % E), y = (int)((loc / E) % E), z = (int)(loc / (E * E));
+                const int64_t b2 = (src / cells) * tiles + (((z >> 3) << 2) | ((y >> 3) << 1) | (x >> 3));
+                const int ci = x & 7, cj = y & 7, ck = z & 7;
+                bool same = true;
+                for (int dk = -1; dk <= 1 && same; ++dk)
+                    for (int dj = -1; dj <= 1 && same; ++dj)
+                        for (int di = -1; di <= 1 && same; ++di)
+                            same = desc(b, i + di, j + dj, k + dk) == desc(b2, ci + di, cj + dj, ck + dk);
+                if (same) out = (int32_t)(b2 * mlp::NSLOT + (ck * NX + cj) * NX + ci);
+            }
+            alias[b * NGS + s] = out;
+        }
+    }
+    return HYDRO_OK;
 }
 
 int hydro_reflux_map(const hydro_tree *t, int32_t *face_flags, int32_t *entries, int32_t *n_entries) {

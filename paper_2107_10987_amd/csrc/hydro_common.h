@@ -66,6 +66,7 @@ struct StageArgs {
     const float *mlp_off;     // [n][7][26][896] learned point values as binary32 offsets
                               // from the cell value (field, dir, slot)
     const uint8_t *mlp_ok;    // [n][896]
+    const int32_t *mlp_alias; // [n][384] shared rows of ghost-slab cells (block * 896 + slot), or null
     // flux correction at coarse/fine faces (null: none)
     const int32_t *face_flags;  // [n]: bits 0-5 corrected faces, 8-13 faces kept for a coarser leaf
     double *bflux;              // [n][6][7][64] Simpson flux of flagged boundary faces

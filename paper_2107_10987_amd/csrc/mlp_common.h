@@ -98,6 +98,8 @@ struct MlpInfer {
     const int32_t *prolong;     // linear-prolongation rows (or null)
     int n_prolong;
     float *yraw;                // null, or [blocks][7][896][26]: the network's outputs per row
+    const int32_t *alias;       // null, or [blocks][384]: ghost-slab rows shared with another
+                                // block (block * 896 + slot); all-shared slabs of the launch are skipped
 };
 
 }  // namespace mlp

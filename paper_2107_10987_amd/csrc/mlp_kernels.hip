@@ -469,9 +469,24 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
     __shared__ __attribute__((aligned(16))) float bias[BI_SIZE];   //  2,176 B
     __shared__ unsigned long long fails[NF];
     __shared__ int4 otab[4][4];
+    __shared__ int shared_s;
     const int item = xcd_leaf(blockIdx.x, gridDim.x);
     const int blk = m.leaf0 + item / ICHUNK, chunk = item % ICHUNK;
     const int tid = threadIdx.x, lane = tid & 63, f = tid >> 6;
+    if (!VAL64 && m.alias && chunk >= NX) {
+        // a ghost slab whose every cell shares its row with a block of this
+        // launch (whose pre-pass computes it as an interior cell) is skipped:
+        // the stage reads those rows there
+        if (tid < 64) {
+            const int al = m.alias[(size_t)blk * (NSLOT - NC) + 64 * (chunk - NX) + tid];
+            const int tb = al / NSLOT;
+            const bool in = al >= 0 && tb >= m.leaf0 && tb < m.leaf0 + (int)(gridDim.x / ICHUNK);
+            const bool all = __all(in);
+            if (tid == 0) shared_s = all;
+        }
+        __syncthreads();
+        if (shared_s) return;
+    }
     for (int i = tid; i < WBI_SIZE / 8; i += 64 * NF) ((uint4 *)W)[i] = ((const uint4 *)m.wbi)[i];
     for (int i = tid; i < BI_SIZE; i += 64 * NF) bias[i] = m.bi[i];
     // chunk geometry: box origin (o0, o1, o2), extents (d0, d1, 3 or 10)
@@ -663,7 +678,9 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
         for (int ff = 0; ff < NF; ++ff) any |= fails[ff];
         const bool bad = (any >> tid) & 1ull;
         m.cell_ok[(size_t)blk * NSLOT + 64 * chunk + tid] = bad ? 0 : 1;
-        if (tid == 0 && any) atomicAdd(m.fb_count, (unsigned long long)__popcll(any));
+        // statistics count each block's interior cells (a ghost-slab cell is
+        // counted in the block it belongs to)
+        if (tid == 0 && any && chunk < NX) atomicAdd(m.fb_count, (unsigned long long)__popcll(any));
     }
 }
 

@@ -703,9 +703,19 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
     const int cB = pidx(bi, bj, bk);
     ValSrc src{nullptr};
     if (LEARNED && a.mlp_off) {
-        const int slot = mlp::slot_of(bi, bj, bk);
-        if (a.mlp_ok[(size_t)leaf * mlp::NSLOT + slot])
-            src.off = a.mlp_off + (size_t)leaf * NF * 26 * mlp::NSLOT + slot;
+        int blk = leaf, slot = mlp::slot_of(bi, bj, bk);
+        if (slot >= NC && a.mlp_alias) {
+            // a ghost-slab cell whose row another block of this launch holds
+            // (the pre-pass may have skipped this block's copy)
+            const int al = a.mlp_alias[(size_t)leaf * (mlp::NSLOT - NC) + slot - NC];
+            const int tb = al / mlp::NSLOT;
+            if (al >= 0 && tb >= a.leaf0 && tb < a.leaf0 + a.nleaf) {
+                blk = tb;
+                slot = al - tb * mlp::NSLOT;
+            }
+        }
+        if (a.mlp_ok[(size_t)blk * mlp::NSLOT + slot])
+            src.off = a.mlp_off + (size_t)blk * NF * 26 * mlp::NSLOT + slot;
     }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;

@@ -26,7 +26,7 @@ EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_ghost_map_
            "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
            "hydro_mlp_pairs", "hydro_mlp_stats", "hydro_amax_device",
            "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error",
-           "hydro_step_noalloc", "hydro_mlp_values")
+           "hydro_step_noalloc", "hydro_mlp_values", "hydro_mlp_alias_map")
 NOALLOC_MAX_LEAVES = 64
 SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
 NBUCKET = 16
@@ -50,7 +50,8 @@ class Grid(C.Structure):
                 ("U", C.c_void_p), ("dx", C.c_void_p), ("origin", C.c_void_p),
                 ("ghost_map", C.c_void_p), ("omega", C.c_double), ("gamma", C.c_double),
                 ("stream", C.c_void_p), ("face_flags", C.c_void_p), ("reflux", C.c_void_p),
-                ("n_reflux", C.c_int32), ("prolong", C.c_void_p), ("n_prolong", C.c_int32)]
+                ("n_reflux", C.c_int32), ("prolong", C.c_void_p), ("n_prolong", C.c_int32),
+                ("mlp_alias", C.c_void_p)]
 
 
 class Tree(C.Structure):
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     ip = C.POINTER(C.c_int32)
     L.hydro_reflux_map.argtypes = [C.POINTER(Tree), ip, ip, ip]
     L.hydro_ghost_map_linear.argtypes = [C.POINTER(Tree), ip, ip, C.c_int32, ip]
+    L.hydro_mlp_alias_map.argtypes = [C.POINTER(Tree), ip, ip]
     L.hydro_step.argtypes = [vp, C.POINTER(Grid), C.c_double, dp]
     L.hydro_stage.argtypes = [vp, C.POINTER(Grid), C.c_int, C.c_double, vp, vp, vp, vp]
     L.hydro_signal_speed.argtypes = [vp, C.POINTER(Grid), vp]
@@ -130,6 +132,23 @@ def ghost_map(tree) -> np.ndarray:
     shape = (tree.n, NGHOST) if tree.leaf_edge == NX else (tree.n, 8, NGHOST)
     out = np.empty(shape, dtype=np.int32)
     rc = L.hydro_ghost_map(C.byref(t), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
+    return out
+
+
+def mlp_alias_map(tree, gmap) -> np.ndarray:
+    """Learned-reconstruction rows that blocks share (hydro_mlp_alias_map):
+    int32 [n T][384], block * 896 + slot or -1, from the tree and its host
+    ghost map."""
+    L = load()
+    t, _keep = _tree_struct(tree)
+    gm = np.ascontiguousarray(gmap, dtype=np.int32)
+    T = 1 if tree.leaf_edge == NX else 8
+    assert gm.size == tree.n * T * NGHOST
+    out = np.empty((tree.n * T, 384), dtype=np.int32)
+    ip = C.POINTER(C.c_int32)
+    rc = L.hydro_mlp_alias_map(C.byref(t), gm.ctypes.data_as(ip), out.ctypes.data_as(ip))
     if rc:
         raise HydroError(rc, L.hydro_last_error(None).decode())
     return out
@@ -233,8 +252,11 @@ class Hydro:
 
     # -- grids ---------------------------------------------------------------
     def grid(self, tree, U, omega: float, gamma: float, launch_off=None, stream=None,
-             gmap=None) -> "DeviceGrid":
-        return DeviceGrid(self, tree, U, omega, gamma, launch_off, stream, gmap)
+             gmap=None, mlp_alias: bool = True) -> "DeviceGrid":
+        """mlp_alias: with learned reconstruction, pass the shared-row table
+        (hydro_mlp_alias_map) so the pre-pass skips ghost slabs other blocks
+        compute."""
+        return DeviceGrid(self, tree, U, omega, gamma, launch_off, stream, gmap, mlp_alias)
 
     # -- calls ---------------------------------------------------------------
     def step(self, g: "DeviceGrid", dt: float, want_amax: bool = True):
@@ -353,7 +375,8 @@ class DeviceGrid:
     """Device-resident mesh of one step: U, dx, origin and ghost map as torch
     tensors, plus the C struct that points at them."""
 
-    def __init__(self, hy: Hydro, tree, U, omega, gamma, launch_off=None, stream=None, gmap=None):
+    def __init__(self, hy: Hydro, tree, U, omega, gamma, launch_off=None, stream=None, gmap=None,
+                 mlp_alias: bool = True):
         torch = hy.torch
         dev = torch.device("cuda", hy.device)
         a = tree.arrays()
@@ -377,6 +400,10 @@ class DeviceGrid:
         else:
             gm = ghost_map(tree)
         self.gmap = torch.as_tensor(gm, device=dev)
+        self.alias = None
+        if hy.learned and mlp_alias:
+            gh = gm.cpu().numpy() if isinstance(gm, torch.Tensor) else np.asarray(gm)
+            self.alias = torch.as_tensor(mlp_alias_map(tree, gh), device=dev)
         self.stream = stream
         if launch_off is not None:
             self._off = np.ascontiguousarray(launch_off, dtype=np.int32)
@@ -395,4 +422,4 @@ class DeviceGrid:
         self.c = Grid(tree.n, nl, offp, _ptr(self.U), _ptr(self.dx), _ptr(self.origin),
                       _ptr(self.gmap), float(omega), float(gamma), s or None,
                       _ptr(self.flags) or None, (_ptr(self.reflux) if nr else 0) or None, nr,
-                      _ptr(self.ptable) or None, npro)
+                      _ptr(self.ptable) or None, npro, _ptr(self.alias) or None)

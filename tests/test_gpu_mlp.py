@@ -274,7 +274,7 @@ def test_learned_graph_replay_matches_eager_and_counts_cells(torch, trained):
             assert dte.item() == dtg.item(), r
         ce, fe = eager.mlp_stats()
         cg, fg = graph.mlp_stats()
-        assert ce == cg == 2 * 2 * 2 * w.n * 896
+        assert ce == cg == 2 * 2 * 2 * w.n * 512        # interior cells per pre-pass
         assert fe == fg
     finally:
         eager.close()
@@ -305,3 +305,40 @@ def test_learned_uneven_launches_match_one_launch(torch, trained):
     finally:
         one.close()
         many.close()
+
+
+@pytest.mark.parametrize("case", ["polytrope-uneven", "sedov-leaf16"])
+def test_shared_ghost_rows_match_own_rows(torch, trained, case):
+    # with the shared-row table the pre-pass skips ghost slabs whose rows
+    # other blocks of the same launch compute, and the stage reads them
+    # there: the result and the statistics are those of the full pre-pass
+    from paper_2107_10987_amd.hydro import Hydro
+    print(f"case: learned path with and without shared ghost rows, {case}", flush=True)
+    if case == "polytrope-uneven":
+        w = rotating_polytrope()
+        off, kw = uneven_batches(w.n), {}
+    else:
+        w = sedov_uniform(2, leaf_edge=16)
+        off, kw = None, {"leaf_edge": 16}
+    own = Hydro(max_leaves=w.n, schedule="column", learned=True, **kw)
+    shr = Hydro(max_leaves=w.n, schedule="column", learned=True, **kw)
+    try:
+        own.mlp_load(trained)
+        shr.mlp_load(trained)
+        ga = own.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off,
+                      mlp_alias=False)
+        gb = shr.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        assert ga.alias is None and gb.alias is not None and bool((gb.alias >= 0).any())
+        a = own.signal_speed(ga).cpu().numpy()
+        dt = float(w.cfl * np.min(w.tree.dx / a))
+        own.mlp_stats()                       # (counts restart from here)
+        shr.mlp_stats()
+        for _ in range(2):
+            aa = own.step(ga, dt)
+            ab = shr.step(gb, dt)
+            assert np.array_equal(aa, ab)
+        assert torch.equal(ga.U, gb.U)
+        assert own.mlp_stats() == shr.mlp_stats()
+    finally:
+        own.close()
+        shr.close()

@@ -92,7 +92,7 @@ def test_flat_neighbourhood_passes_through(oracle_mod):
     w = sedov_uniform(4)
     P = _block_of(w, leaf=0)          # a corner leaf far from the blast: uniform
     V, needed, fb = oracle_mod.learned_values(P, _params(7))
-    assert needed == 896 and fb == 0
+    assert needed == 512 and fb == 0          # interior cells are counted
     for f in range(7):
         assert np.all(V[:, :, f] == P[f, 3, 3, 3])
 
@@ -200,7 +200,7 @@ def test_rows_are_the_table_before_fallback(oracle_mod):
     y, val, ok, flat = oracle_mod.learned_rows(P, p)
     V, nn, nf = oracle_mod.learned_values(P, p)
     Vp = oracle_mod.reconstruct_values(P)
-    assert nn == 896
+    assert nn == 512
     rng = np.random.default_rng(10)
     for c in rng.choice(1000, 60, replace=False):
         k, j, i = c // 100 - 1, (c // 10) % 10 - 1, c % 10 - 1
@@ -216,9 +216,9 @@ def test_rows_are_the_table_before_fallback(oracle_mod):
             assert ok[c, f] == oracle_mod.mlp_row_ok(nb, v, f)
         want = val[c].T if ok[c].all() else Vp[c]
         assert np.array_equal(V[c], want)
-    needed = [c for c in range(1000)
-              if sum(v < 0 or v > 7 for v in (c % 10 - 1, (c // 10) % 10 - 1, c // 100 - 1)) <= 1]
-    assert nf == sum(not ok[c].all() for c in needed)
+    interior = [c for c in range(1000)
+                if sum(v < 0 or v > 7 for v in (c % 10 - 1, (c // 10) % 10 - 1, c // 100 - 1)) == 0]
+    assert nf == sum(not ok[c].all() for c in interior)
 
 
 def _rz_ok(o, x):
