@@ -93,8 +93,8 @@ def parse(argv=None):
                     help="before anything else, one untimed device copy of this many MiB from a freshly "
                          "written buffer (the reference kernel for HBM counter calibration)")
     ap.add_argument("--profile", default=None,
-                    choices=["binary-plain", "binary-learned", "sedov64", "sedov256", "polytrope-plain",
-                             "polytrope-learned"],
+                    choices=["binary-plain", "binary-learned", "sedov64", "sedov256", "sedov64-leaf16",
+                             "sedov64-old", "polytrope-plain", "polytrope-learned"],
                     help="run only this workload's kernels, a few eager steps (for counter runs)")
     ap.add_argument("--reduce-trace", metavar="TRACE_DIR",
                     help="per-kernel, per-grid-size dispatch counts and mean durations of a rocprofv3 "
@@ -685,12 +685,15 @@ def profile_mode(torch, args):
         w = rotating_polytrope()
     elif name == "sedov256":
         w = sedov_uniform(32)
+    elif name == "sedov64-leaf16":
+        w = sedov_uniform(4, leaf_edge=16)
     else:
         w = sedov_uniform(8)
     off = None
     if args.copy_probe_mib > 0:
         copy_probe(torch, args.copy_probe_mib)
-    hy = Hydro(max_leaves=w.n, schedule="column", learned=params is not None)
+    hy = Hydro(max_leaves=w.n, schedule="column", learned=params is not None, centre_only=name == "sedov64-old",
+               leaf_edge=w.tree.leaf_edge)
     try:
         if params is not None:
             hy.mlp_load(params)
