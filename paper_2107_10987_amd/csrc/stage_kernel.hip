@@ -291,12 +291,15 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Ghost-padded 14^3 block of block b into LDS (nt threads cooperate): its
+// Ghost-padded 14^3 block of block b into LDS (NTH threads cooperate): its
 // 8^3 cells from U, its ghost cells through the ghost map (a copy, or the mean
-// of the 2x2x2 cells of a finer leaf, summed in z, y, x order).
-// Ghost-padded block of block b into LDS.  Each thread first issues all of
-// its interior loads, then all of its ghost-map reads, so the latencies
-// overlap instead of adding up loop iteration by loop iteration.
+// of the 2x2x2 cells of a finer leaf, summed in z, y, x order, or a
+// prolongation row).  The loads are issued in two waves: first every load
+// whose address is known (the block's own cells, the ghost-map entries and
+// their padded positions), then the copied ghost values, all into registers
+// before any LDS store, so that each thread waits on memory about twice
+// rather than once per ghost cell.  Threads past the end of a range load and
+// store the last element again (the same value to the same place).
 template <int NTH>
 __device__ __forceinline__ void gather_block(double *P, const double *U, const int32_t *gm, int b,
                                              int ts, int lg, const int32_t *prolong, int n_prolong,
@@ -304,40 +307,49 @@ __device__ __forceinline__ void gather_block(double *P, const double *U, const i
     const double *Ub = U + block_base(b, ts, lg);
     const size_t fs = (size_t)1 << (3 * lg);
     constexpr int NI = (LEAF_STRIDE + NTH - 1) / NTH;
+    constexpr int NGI = (NG + NTH - 1) / NTH;
+    const int32_t *g = gm + (size_t)b * NG;
     double v[NI];
+    int srcs[NGI], pads[NGI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int e = min(tid + i * NTH, LEAF_STRIDE - 1);   // (a clamped, in-bounds read)
+        const int e = min(tid + i * NTH, LEAF_STRIDE - 1);
         const int f = e >> 9, c = e & (NC - 1);
         v[i] = Ub[f * fs + block_cell(c, lg)];
     }
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int e = tid + i * NTH;
-        const int f = e >> 9, c = e & (NC - 1);
-        if (e < LEAF_STRIDE) P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = v[i];
+    for (int i = 0; i < NGI; ++i) {
+        const int sl = min(tid + i * NTH, NG - 1);
+        srcs[i] = g[sl];
+        pads[i] = c_ghost_pad[sl];
     }
-    const int32_t *g = gm + (size_t)b * NG;
+    // copied ghost values (the common case) straight into registers; means
+    // and prolongation rows are formed after
     const int E = 1 << lg, E2 = E * E;
-    constexpr int NGI = (NG + NTH - 1) / NTH;
-    int srcs[NGI];
+    double gv[NGI][NF];
 #pragma unroll
     for (int i = 0; i < NGI; ++i) {
-        srcs[i] = g[min(tid + i * NTH, NG - 1)];
+        if (srcs[i] >= 0) {
+            const double *q = U + src_offset(srcs[i], lg);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) gv[i][f] = q[f * fs];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = min(tid + i * NTH, LEAF_STRIDE - 1);
+        const int f = e >> 9, c = e & (NC - 1);
+        P[f * NP + pidx(c & 7, (c >> 3) & 7, c >> 6)] = v[i];
     }
 #pragma unroll
     for (int i = 0; i < NGI; ++i) {
-        const int s = tid + i * NTH;
-        if (s >= NG) continue;
         const int src = srcs[i];
-        const int p = c_ghost_pad[s];
         if (src >= 0) {
-            const double *q = U + src_offset(src, lg);
 #pragma unroll
-            for (int f = 0; f < NF; ++f) P[f * NP + p] = q[f * fs];
+            for (int f = 0; f < NF; ++f) P[f * NP + pads[i]] = gv[i][f];
         } else if (src < -PROLONG_BASE) {
 #pragma unroll 1
-            for (int f = 0; f < NF; ++f) P[f * NP + p] = ghost_value(U, src, f, lg, prolong, n_prolong);
+            for (int f = 0; f < NF; ++f) P[f * NP + pads[i]] = ghost_value(U, src, f, lg, prolong, n_prolong);
         } else {
             const double *q = U + src_offset(-src - 1, lg);
 #pragma unroll
@@ -352,7 +364,7 @@ __device__ __forceinline__ void gather_block(double *P, const double *U, const i
                 acc = acc + qf[E2 + 1];
                 acc = acc + qf[E2 + E];
                 acc = acc + qf[E2 + E + 1];
-                P[f * NP + p] = acc * 0.125;
+                P[f * NP + pads[i]] = acc * 0.125;
             }
         }
     }
