@@ -112,3 +112,53 @@ def test_headline_configuration_step_parity(torch, request, name):
         l0 = int(l0)
         parity.check(got[l0:l0 + 8], Uo[l0:l0 + 8], o, w.U, size=7, l0=l0, l1=l0 + 8,
                      label=f"{name} leaves [{l0}, {l0 + 8})")
+
+
+def _constant_network(seed=11, scale=0.6):
+    """Output weights zero: the network outputs its biases exactly on both
+    sides, so the learned point values are the same arithmetic on the GPU and
+    in the oracle (bit for bit)."""
+    rng = np.random.default_rng(seed)
+    p = (rng.normal(size=8090) * 0.3).astype(np.float32)
+    p[6400:8064] = 0.0
+    p[8064:] = rng.uniform(-scale, scale, 26).astype(np.float32)
+    return p
+
+
+def test_binary_learned_stage_sampled_parity(torch, binary):
+    """The learned configuration at full size: all 32,768 leaves in one
+    launch per stage, the inference pre-pass with the shared ghost rows, the
+    learned column walk; stage 1 against the oracle's learned stage on
+    sampled leaf ranges, per field and per element."""
+    import oracle
+    import parity
+    from paper_2107_10987_amd.hydro import Hydro
+    w = binary
+    p = _constant_network()
+    print("case: binary-32768 learned stage 1, constant-output network, shared ghost rows", flush=True)
+    hy = Hydro(max_leaves=w.n, schedule="auto", learned=True)
+    try:
+        hy.mlp_load(p)
+        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma)
+        assert g.alias is not None
+        a = hy.signal_speed(g).cpu().numpy()
+        dt = float(w.cfl * np.min(w.tree.dx / a))
+        hy.mlp_stats()
+        U1 = torch.empty_like(g.U)
+        am = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+        hy.stage(g, 1, dt, g.U, None, U1, am)
+        cells, fb = hy.mlp_stats()
+        U1 = U1.cpu().numpy()
+        am = am.cpu().numpy()
+    finally:
+        hy.close()
+    assert cells == w.n * 512 and 0 < fb < cells
+    o = oracle.Oracle(w.tree, w.gamma, w.omega)
+    rng = np.random.default_rng(13)
+    for l0 in np.sort(rng.choice(w.n - 8, 8, replace=False)):
+        l0 = int(l0)
+        Uo, ao, fbo = o.stage_learned(p, 1, dt, w.U, l0=l0, l1=l0 + 8)
+        parity.check(U1[l0:l0 + 8], Uo, o, w.U, size=7, l0=l0, l1=l0 + 8,
+                     label=f"binary learned leaves [{l0}, {l0 + 8})")
+        assert np.abs(am[l0:l0 + 8] - ao).max() <= TOL * ao.max()
+    print(f"binary learned: {fb} of {cells} interior cells fall back", flush=True)
