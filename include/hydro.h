@@ -375,6 +375,15 @@ int hydro_check(hydro_t *h, void *stream);
  * support (section V-A1 reports per-kernel times); not part of the method. */
 int hydro_timing(hydro_t *h, int enable, double *total_ms, int64_t *launches);
 
+/* The attainable FP64 vector rate of the current device, for the rooflines:
+ * blocks workgroups of 256 threads, each thread eight independent chains of
+ * iters fused multiply-adds a = a m + c (16 iters flops per thread), chain k
+ * of thread t starting at t + k; out (device double [blocks * 256]) receives
+ * each thread's sum of its chains (with m = c = 1: 8 t + 28 + 8 iters).
+ * Asynchronous on stream; time it with events.  Errors set
+ * hydro_last_error(NULL).  Measurement support; not part of the method. */
+int hydro_fp64_probe(double *out, int32_t blocks, int32_t iters, double m, double c, void *stream);
+
 /* Text of a return code, and of the last error of a handle (NULL: of the
  * last hydro_create).  Library support; not part of the method. */
 const char *hydro_strerror(int code);

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libhydro.so")
 ARCH = "gfx950"
 
-SOURCES = ["stage_kernel.hip", "mlp_kernels.hip", "hydro_api.hip", "hydro_noalloc.hip"]
+SOURCES = ["stage_kernel.hip", "mlp_kernels.hip", "hydro_api.hip", "hydro_noalloc.hip", "probe_kernels.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

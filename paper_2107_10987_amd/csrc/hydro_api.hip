@@ -610,6 +610,9 @@ int build_ghost_map(const hydro_tree *t, int32_t *map, int32_t *table, int32_t c
 hipError_t hydro_internal_ghost_table(int dev) { return ensure_ghost_table(dev); }
 void hydro_internal_set_error(const char *msg) { g_create_err = msg; }
 
+// Launcher of the attainable-rate probe (probe_kernels.hip).
+hipError_t hydro_launch_fp64_probe(double *out, int blocks, int iters, double m, double c, hipStream_t s);
+
 extern "C" {
 
 int hydro_create(const hydro_params *p, hydro_t **out) {
@@ -1059,6 +1062,13 @@ int hydro_check(hydro_t *h, void *stream) {
     int rc = set_device(h);
     if (rc) return rc;
     return read_status(h, (hipStream_t)stream);
+}
+
+int hydro_fp64_probe(double *out, int32_t blocks, int32_t iters, double m, double c, void *stream) {
+    if (!out || blocks <= 0 || iters < 0) return fail(nullptr, HYDRO_EINVAL, "null out, blocks <= 0 or iters < 0");
+    if (((uintptr_t)out & 7u) != 0) return fail(nullptr, HYDRO_EINVAL, "out is misaligned");
+    hipError_t e = hydro_launch_fp64_probe(out, blocks, iters, m, c, (hipStream_t)stream);
+    return e == hipSuccess ? HYDRO_OK : fail(nullptr, HYDRO_EHIP, std::string("probe launch: ") + hipGetErrorString(e));
 }
 
 int hydro_timing(hydro_t *h, int enable, double *total_ms, int64_t *launches) {

@@ -26,7 +26,7 @@ EXPORTS = ("hydro_create", "hydro_destroy", "hydro_ghost_map", "hydro_ghost_map_
            "hydro_mlp_save", "hydro_mlp_forward", "hydro_mlp_grad", "hydro_mlp_train_step",
            "hydro_mlp_pairs", "hydro_mlp_stats", "hydro_amax_device",
            "hydro_check", "hydro_timing", "hydro_strerror", "hydro_last_error",
-           "hydro_step_noalloc", "hydro_mlp_values", "hydro_mlp_alias_map")
+           "hydro_step_noalloc", "hydro_mlp_values", "hydro_mlp_alias_map", "hydro_fp64_probe")
 NOALLOC_MAX_LEAVES = 64
 SCHEDULES = {"auto": 0, "face": 1, "column": 2, "persistent": 3, "tiled": 4}
 NBUCKET = 16
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.hydro_last_error.argtypes = [vp]
     L.hydro_last_error.restype = C.c_char_p
     L.hydro_step_noalloc.argtypes = [C.POINTER(Grid), C.c_double, C.c_double, C.c_double, vp, C.c_int]
+    L.hydro_fp64_probe.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.hydro_amax_device.restype = vp
@@ -193,6 +194,16 @@ def reflux_map(tree):
 
 def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
+
+
+def fp64_probe(out, blocks: int, iters: int, m: float = 1.0, c: float = 1.0, stream=None):
+    """hydro_fp64_probe into the device tensor out (float64, >= blocks*256)."""
+    L = load()
+    assert out.dtype.is_floating_point and out.element_size() == 8 and out.numel() >= blocks * 256
+    s = None if stream is None else int(stream.cuda_stream) or None
+    rc = L.hydro_fp64_probe(_ptr(out), int(blocks), int(iters), float(m), float(c), s)
+    if rc:
+        raise HydroError(rc, L.hydro_last_error(None).decode())
 
 
 def step_noalloc(g: "DeviceGrid", dt: float, eta1: float = 1e-3, eta2: float = 1e-1, amax=None,

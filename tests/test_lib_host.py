@@ -21,7 +21,7 @@ needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libhydro.so not 
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(hydro_[a-z_0-9]+)\s*\(", src)))
 
 
 @needs_lib
