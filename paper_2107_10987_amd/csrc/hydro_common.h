@@ -63,8 +63,8 @@ struct StageArgs {
     int *leaf_done;           // [n] axis tiles finished per leaf (zero between launches)
     double *tile_amax;        // [n][3]
     // learned reconstruction (null: plain PPM)
-    const float *mlp_off;     // [n][7][26][896] learned point values as binary32 offsets
-                              // from the cell value (field, dir, slot)
+    const float *mlp_off;     // [n][7][13][896][2] learned point values as binary32 offsets
+                              // from the cell value (field, line, slot, +d / -d end)
     const uint8_t *mlp_ok;    // [n][896]
     const int32_t *mlp_alias; // [n][384] shared rows of ghost-slab cells (block * 896 + slot), or null
     // flux correction at coarse/fine faces (null: none)

@@ -38,6 +38,27 @@ __host__ __device__ inline int slot_of(int i, int j, int k) {
     return 512 + 64 * (k < 0 ? 4 : 5) + i + 8 * j;
 }
 
+// The 13 lines of the learned reconstruction in the network's output order,
+// by the 3x3x3 index 9 (dz+1) + 3 (dy+1) + (dx+1) of their +d direction:
+// (1,0,0), (0,1,0), (0,0,1), (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1),
+// (0,1,-1), (1,1,1), (1,1,-1), (1,-1,1), (1,-1,-1).
+constexpr int LINE_DIR[13] = {14, 16, 22, 17, 11, 23, 5, 25, 7, 26, 8, 20, 2};
+
+// Line of each 3x3x3 direction index: l, or l + 16 where the index is the
+// line's -d end (-1 for the centre).
+struct LineOfDir {
+    int v[27];
+};
+constexpr LineOfDir make_line_of_dir() {
+    LineOfDir t{};
+    for (int k = 0; k < 27; ++k) t.v[k] = -1;
+    for (int l = 0; l < 13; ++l) {
+        t.v[LINE_DIR[l]] = l;
+        t.v[26 - LINE_DIR[l]] = l + 16;
+    }
+    return t;
+}
+
 // Binary32 rounding toward zero of x: the nearest binary32, stepped one unit
 // toward zero where it came out larger in magnitude (sign-magnitude bits:
 // one less in the integer view is one unit smaller in magnitude).
@@ -88,8 +109,8 @@ struct MlpInfer {
     const int32_t *gmap;        // [blocks][2232]
     const uint16_t *wbi;        // bf16 inference image
     const float *bi;            // its float32 biases
-    float *off;                 // [blocks][7][26][896] point values as offsets from the cell
-                                // value (field, dir, slot), or null
+    float *off;                 // [blocks][7][13][896][2] point values as offsets from the cell
+                                // value (field, line, slot, +d / -d end), or null
     double *val;                // the same as FP64 point values, or null
     uint8_t *cell_ok;           // [blocks][896]
     unsigned long long *fb_count;  // cells that fell back to plain PPM

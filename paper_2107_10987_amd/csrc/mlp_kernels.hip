@@ -330,7 +330,9 @@ namespace {
 
 // the +d direction (index into the 3x3x3 neighbourhood, 13 = centre) of the
 // 13 lines in the network's output order
-__constant__ int c_lines[13] = {14, 16, 22, 17, 11, 23, 5, 25, 7, 26, 8, 20, 2};
+__constant__ int c_lines[13] = {LINE_DIR[0], LINE_DIR[1], LINE_DIR[2],  LINE_DIR[3],  LINE_DIR[4],
+                                LINE_DIR[5], LINE_DIR[6], LINE_DIR[7],  LINE_DIR[8],  LINE_DIR[9],
+                                LINE_DIR[10], LINE_DIR[11], LINE_DIR[12]};
 
 // hidden unit at k position kap of a 64-wide layer input
 __device__ __forceinline__ int hidden_of(int kap) {
@@ -540,7 +542,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
     }
     __syncthreads();
     const double *bx = box[f];
-    float *oout = VAL64 ? nullptr : m.off + ((size_t)blk * NF + f) * 26 * NSLOT;
+    float2 *oout = VAL64 ? nullptr : (float2 *)m.off + ((size_t)blk * NF + f) * 13 * NSLOT;
     double *vout = VAL64 ? m.val + ((size_t)blk * NF + f) * 26 * NSLOT : nullptr;
     unsigned long long wfail = 0;
 #pragma unroll 1
@@ -579,8 +581,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
                     vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc;
                     vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc;
                 } else {
-                    oout[(size_t)(lrow[t] & 255) * NSLOT + slot] = 0.0f;
-                    oout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = 0.0f;
+                    oout[(size_t)(4 * q + t) * NSLOT + slot] = float2{0.0f, 0.0f};
                 }
             }
             continue;
@@ -662,8 +663,7 @@ __global__ void __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(7)
                 vout[(size_t)(lrow[t] & 255) * NSLOT + slot] = qc + (double)oR;
                 vout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = qc + (double)oL;
             } else {
-                oout[(size_t)(lrow[t] & 255) * NSLOT + slot] = oR;
-                oout[(size_t)(lrow[t] >> 8) * NSLOT + slot] = oL;
+                oout[(size_t)(4 * q + t) * NSLOT + slot] = float2{oR, oL};
             }
         }
         const unsigned long long bad = __ballot(!ok);

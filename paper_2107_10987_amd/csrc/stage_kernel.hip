@@ -599,31 +599,35 @@ __device__ __forceinline__ void line_ends(const double *P, int c, int dx, int dy
 // Where a lane's point values come from: plain PPM, or (learned
 // reconstruction, cell passed the FP64 check) the inference pre-pass.
 struct ValSrc {
-    const float *off;      // this cell's values as offsets from its own value, (field f,
-                           // dir d) at off[(26 f + d) * 896], or null for plain PPM
+    const float2 *off;     // this cell's values as offsets from its own value: both ends
+                           // (+d, -d) of line l of field f at off[(13 f + l) * 896], or
+                           // null for plain PPM
 };
 
-__device__ __forceinline__ int dir26_of(int dx, int dy, int dz) {
-    const int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
-    return k < 13 ? k : k - 1;
+// Line (0..12) of each 3x3x3 direction index, + 16 at the line's -d end.
+__constant__ mlp::LineOfDir c_line_of = mlp::make_line_of_dir();
+
+// Offsets of the two ends of the line through a cell in direction
+// (dx, dy, dz): o.x at +d, o.y at -d of that direction.
+__device__ __forceinline__ float2 line_offsets(const float2 *off, int f, int dx, int dy, int dz) {
+    const int lt = c_line_of.v[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)];
+    const float2 v = off[(size_t)(f * 13 + (lt & 15)) * mlp::NSLOT];
+    return (lt & 16) ? float2{v.y, v.x} : v;
 }
+
 
 template <bool LEARNED>
 __device__ __forceinline__ void line_vals(const double *P, int c, int dx, int dy, int dz,
                                           const ValSrc &src, double pos[NF], double neg[NF]) {
     if (LEARNED && src.off) {
-        const int dp = dir26_of(dx, dy, dz), dm = dir26_of(-dx, -dy, -dz);
-        float op[NF], om[NF];
+        float2 o[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            op[f] = src.off[(size_t)(f * 26 + dp) * mlp::NSLOT];
-            om[f] = src.off[(size_t)(f * 26 + dm) * mlp::NSLOT];
-        }
+        for (int f = 0; f < NF; ++f) o[f] = line_offsets(src.off, f, dx, dy, dz);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const double qc = P[f * NP + c];
-            pos[f] = qc + (double)op[f];
-            neg[f] = qc + (double)om[f];
+            pos[f] = qc + (double)o[f].x;
+            neg[f] = qc + (double)o[f].y;
         }
     } else {
         line_ends(P, c, dx, dy, dz, pos, neg);
@@ -638,23 +642,19 @@ __device__ __forceinline__ void pair_vals(const double *P, int c, int x1, int y1
                                           const ValSrc &src, double pos1[NF], double neg1[NF], double pos2[NF],
                                           double neg2[NF]) {
     if (LEARNED && src.off) {
-        const int p1 = dir26_of(x1, y1, z1), m1 = dir26_of(-x1, -y1, -z1);
-        const int p2 = dir26_of(x2, y2, z2), m2 = dir26_of(-x2, -y2, -z2);
-        float o[4][NF];
+        float2 o1[NF], o2[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            o[0][f] = src.off[(size_t)(f * 26 + p1) * mlp::NSLOT];
-            o[1][f] = src.off[(size_t)(f * 26 + m1) * mlp::NSLOT];
-            o[2][f] = src.off[(size_t)(f * 26 + p2) * mlp::NSLOT];
-            o[3][f] = src.off[(size_t)(f * 26 + m2) * mlp::NSLOT];
+            o1[f] = line_offsets(src.off, f, x1, y1, z1);
+            o2[f] = line_offsets(src.off, f, x2, y2, z2);
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const double qc = P[f * NP + c];
-            pos1[f] = qc + (double)o[0][f];
-            neg1[f] = qc + (double)o[1][f];
-            pos2[f] = qc + (double)o[2][f];
-            neg2[f] = qc + (double)o[3][f];
+            pos1[f] = qc + (double)o1[f].x;
+            neg1[f] = qc + (double)o1[f].y;
+            pos2[f] = qc + (double)o2[f].x;
+            neg2[f] = qc + (double)o2[f].y;
         }
     } else {
         line_ends(P, c, x1, y1, z1, pos1, neg1);
@@ -727,7 +727,7 @@ __device__ __forceinline__ void column_axis(int N, const double *P, int col, int
             }
         }
         if (a.mlp_ok[(size_t)blk * mlp::NSLOT + slot])
-            src.off = a.mlp_off + (size_t)blk * NF * 26 * mlp::NSLOT + slot;
+            src.off = (const float2 *)a.mlp_off + (size_t)blk * NF * 13 * mlp::NSLOT + slot;
     }
     const double xB = ox + (double)bi * dx;
     const double yB = oy + (double)bj * dx;
