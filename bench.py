@@ -162,6 +162,28 @@ def mfma_roofline(cells: int, seconds: float, traffic=None):
             "rows_per_launch": 7 * cells}
 
 
+def learned_table_bytes(g) -> int:
+    """Bytes of the learned values a stage over all of g's blocks needs, each
+    once: the 13 lines x 7 fields of every interior cell as stored (two
+    binary32 offsets, 8 B), and for every face-adjacent ghost cell whose row
+    no block of the launch holds as its own, the 9 lines crossing that face at
+    the one end the face uses (4 B); a shared ghost row is the owner's
+    interior row, counted there."""
+    blocks = g.gmap.numel() // 2232
+    own = blocks * 384 if g.alias is None else int((g.alias < 0).sum())
+    return blocks * 512 * 13 * 7 * 8 + own * 9 * 7 * 4
+
+
+def hbm_roofline(kernel: str, alg_bytes: float, seconds: float, traffic=None):
+    """HBM fraction of a launch from its algorithmic bytes, with the
+    counter-measured bytes beside it."""
+    ach = alg_bytes / seconds / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "counter_frac": None if not traffic else traffic / seconds / 1e9 / PEAK_HBM_GBS}
+
+
 def hbm_figures(cells: int, seconds: float, traffic=None):
     """Algorithmic HBM rate (140 B per cell-update) and, when the counter
     summary is current, the counter-measured one, against the 8 TB/s peak."""
@@ -478,6 +500,10 @@ def single_launch_leg(torch, args, w, name, params=None, schedule=None, centre_o
                "roofline": fp64_roofline(kernel, w.cells, avg, traffic, flops),
                "hbm": hbm_figures(w.cells, avg, traffic), "dt_after": dt_after}
         if params is not None:
+            # the learned stage is bound by its reads of the learned values
+            out["roofline_fp64"] = out["roofline"]
+            out["roofline"] = hbm_roofline(kernel, BYTES_PER_CELL_UPDATE * w.cells + learned_table_bytes(g),
+                                           avg, traffic)
             cells, fb = hy.mlp_stats()
             out["fallback_fraction"] = fb / max(cells, 1)
             tp = time_prepass(torch, hy, g, s)
@@ -561,6 +587,10 @@ def polytrope_legs(torch, args, params):
                                                    med / 2, traffic),
                          "hbm": hbm_figures(w.cells, med / 2, traffic)}
             if on:
+                out[name]["roofline_fp64"] = out[name]["roofline"]
+                out[name]["roofline"] = hbm_roofline(
+                    kernel + " (whole stage, concurrent launches)",
+                    BYTES_PER_CELL_UPDATE * w.cells + learned_table_bytes(g), med / 2, traffic)
                 cells, fb = hy.mlp_stats()
                 out[name]["fallback_fraction"] = fb / max(cells, 1)
                 g.U.copy_(U0)
@@ -729,27 +759,31 @@ def profile_mode(torch, args):
         w = sedov_uniform(4, leaf_edge=16)
     else:
         w = sedov_uniform(8)
-    off = None
     if args.copy_probe_mib > 0:
         copy_probe(torch, args.copy_probe_mib)
-    hy = Hydro(max_leaves=w.n, schedule="column", learned=params is not None, centre_only=name == "sedov64-old",
-               leaf_edge=w.tree.leaf_edge)
-    try:
-        if params is not None:
-            hy.mlp_load(params)
-        s = torch.cuda.Stream()
-        g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off, stream=s)
-        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-        hy.dt(g, w.cfl, dt_dev)
-        for _ in range(args.steps):
-            hy.step_dev(g, w.cfl, dt_dev)
-        if params is not None:
-            hy.mlp_values(g, into_handle=True)
-        s.synchronize()
-        hy.check(s)
-    finally:
-        hy.close()
-    print(json.dumps({"profile": name, "steps": args.steps, "leaves": w.n}), flush=True)
+    # the learned stage runs with both schedules its autotuner chooses from
+    # for a whole-mesh launch, so that either one's dispatches are counted
+    schedules = ("column", "persistent") if params is not None else ("column",)
+    for sched in schedules:
+        hy = Hydro(max_leaves=w.n, schedule=sched, learned=params is not None,
+                   centre_only=name == "sedov64-old", leaf_edge=w.tree.leaf_edge)
+        try:
+            if params is not None:
+                hy.mlp_load(params)
+            s = torch.cuda.Stream()
+            g = hy.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, stream=s)
+            dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+            hy.dt(g, w.cfl, dt_dev)
+            for _ in range(args.steps):
+                hy.step_dev(g, w.cfl, dt_dev)
+            if params is not None and sched == schedules[0]:
+                hy.mlp_values(g, into_handle=True)
+            s.synchronize()
+            hy.check(s)
+        finally:
+            hy.close()
+    print(json.dumps({"profile": name, "steps": args.steps, "leaves": w.n, "schedules": schedules}),
+          flush=True)
 
 
 # ---------------------------------------------------------------------------
