@@ -385,7 +385,7 @@ def autotuned(hy, g):
         table = hy.autotune(g, path)
         with open(path) as f:
             conc = json.load(f).get("concurrent", -1)
-    return table, {1: "face", 2: "column", 3: "persistent", 4: "tiled"}.get(conc, "table")
+    return table, {1: "face", 2: "column", 3: "persistent", 4: "tiled", 5: "one launch"}.get(conc, "table")
 
 
 def bucket_of(n: int) -> int:
@@ -603,18 +603,24 @@ def polytrope_legs(torch, args, params):
             hy.check(gs)
             med = float(np.min(els[1:])) / args.steps
             tname = f"polytrope-{name}"
-            kernel = KERNEL_OF["column"] if conc in ("column", "table") else KERNEL_OF[conc]
+            merged = conc == "one launch"
+            if merged:   # the tuner replaced the partition by one launch over the mesh
+                kernel = KERNEL_OF[t_[bucket_of(w.n)]]
+                label = kernel + " (whole stage, one launch over the six batches)"
+            else:
+                kernel = KERNEL_OF["column"] if conc in ("column", "table") else KERNEL_OF[conc]
+                label = kernel + " (whole stage, concurrent launches)"
             traffic = measured_traffic(tname, kernel)
             out[name] = {"value": w.cells * 2 / med, "unit": "cell-updates/s", "ms_per_step": med * 1e3,
                          "ms_per_step_host_call": host_med * 1e3,
-                         "launches_per_stage": len(off) - 1, "autotune_concurrent": conc,
-                         "roofline": fp64_roofline(kernel + " (whole stage, concurrent launches)", w.cells,
-                                                   med / 2, traffic),
+                         "launches_per_stage": 1 if merged else len(off) - 1, "batches": len(off) - 1,
+                         "autotune_concurrent": conc,
+                         "roofline": fp64_roofline(label, w.cells, med / 2, traffic),
                          "hbm": hbm_figures(w.cells, med / 2, traffic)}
             if on:
                 out[name]["roofline_fp64"] = out[name]["roofline"]
                 out[name]["roofline"] = hbm_roofline(
-                    kernel + " (whole stage, concurrent launches)",
+                    label,
                     BYTES_PER_CELL_UPDATE * w.cells + learned_table_bytes(g), med / 2, traffic)
                 cells, fb = hy.mlp_stats()
                 out[name]["fallback_fraction"] = fb / max(cells, 1)

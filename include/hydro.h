@@ -248,9 +248,11 @@ int hydro_graph_launch(hydro_t *h, void *stream);
  * NULL) receives it, and cache_path (may be NULL) a JSON copy.  When g has
  * several launches per stage (which run concurrently), whole stages of that
  * partition are also timed with the table and with each schedule for every
- * launch (two interleaved rounds, each candidate's faster one counting), and
- * the fastest of these is used for stages of several launches (kept in the
- * JSON copy as "concurrent": -1 for the table).  Uses only the
+ * launch, and as one launch over all of g's leaves with the table's
+ * schedule (two interleaved rounds, each candidate's faster one counting),
+ * and the fastest of these is used for stages of several launches (kept in
+ * the JSON copy as "concurrent": -1 for the table, 2-4 a schedule, 5 the one
+ * launch).  Uses only the
  * handle's workspace; g->U is read, not written.  Synchronous.  Source:
  * section IV-C3 (the launch configuration and sub-grids per kernel decide
  * GPU utilisation) and section VII-A (tuning the kernels is future work). */

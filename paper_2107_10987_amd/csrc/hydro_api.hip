@@ -40,7 +40,8 @@ struct hydro_t {
     double *bflux = nullptr;   // flux correction: [max_leaves][6][7][64]
     int num_cu = 0;
     int32_t table[HYDRO_NBUCKET];  // schedule per launch-size bucket (HYDRO_SCHED_AUTO)
-    int32_t multi_sched = -1;      // stages of several concurrent launches: one schedule for all (-1: table)
+    int32_t multi_sched = -1;      // stages of several concurrent launches: one schedule for all (-1:
+                                   // table; MULTI_MERGE: one launch over the whole partition)
     bool table_loaded = false;
     std::string arch;
     hipGraph_t graph = nullptr;
@@ -205,10 +206,15 @@ int bucket_of(int nleaf) {
     return b;
 }
 
+// The autotuner's choice for a grid's launch partition that replaces it by
+// one launch over all its leaves (the ranges are consecutive, from 0 to n),
+// with the per-size table's schedule.
+constexpr int MULTI_MERGE = 5;
+
 // Schedule of a launch of nleaf leaves.
 int resolve_schedule(const hydro_t *h, int nleaf, bool concurrent) {
     if (h->p.schedule != HYDRO_SCHED_AUTO) return h->p.schedule;
-    if (concurrent && h->multi_sched >= 0) return h->multi_sched;
+    if (concurrent && h->multi_sched >= 0 && h->multi_sched != MULTI_MERGE) return h->multi_sched;
     if (h->table_loaded) return h->table[bucket_of(nleaf)];
     // built-in rule: spread small launches over (leaf, axis) tiles so they
     // still occupy most compute units; otherwise a workgroup per leaf
@@ -268,14 +274,17 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     a.bflux = reflux ? h->bflux : nullptr;
     hipStream_t s = (hipStream_t)g->stream;
     h->last_stream = s;
-    const int nb = g->n_launch > 0 ? g->n_launch : 1;
+    // the tuned merge of the partition: one launch over leaves 0..n
+    const bool merge = g->n_launch > 1 && h->p.schedule == HYDRO_SCHED_AUTO && h->multi_sched == MULTI_MERGE;
+    const int nlaunch = merge ? 0 : g->n_launch;
+    const int nb = nlaunch > 0 ? nlaunch : 1;
     // the launches of a stage read the same input and write disjoint blocks:
     // they run concurrently on up to 1 + NSIDE streams (the caller's first),
     // each with its own persistent-queue counters, and the caller's stream
     // waits for all of them before anything that follows
     int nonempty = 0;
     for (int b = 0; b < nb; ++b)
-        nonempty += (g->n_launch > 0 ? g->launch_off[b + 1] - g->launch_off[b] : g->n) > 0;
+        nonempty += (nlaunch > 0 ? g->launch_off[b + 1] - g->launch_off[b] : g->n) > 0;
     const int nst = nonempty < 1 + NSIDE ? (nonempty > 0 ? nonempty : 1) : 1 + NSIDE;
     if (nst > 1) {
         hipError_t e = hipEventRecord(h->fork_ev, s);
@@ -285,8 +294,8 @@ int run_stage(hydro_t *h, const hydro_grid *g, int stage, double dt, const doubl
     int k = 0;   // non-empty launches so far
     for (int b = 0; b < nb; ++b) {
         // launches count 8^3 blocks: 2^ts per leaf
-        const int l0 = g->n_launch > 0 ? g->launch_off[b] : 0;
-        const int nl = g->n_launch > 0 ? g->launch_off[b + 1] - l0 : g->n;
+        const int l0 = nlaunch > 0 ? g->launch_off[b] : 0;
+        const int nl = nlaunch > 0 ? g->launch_off[b + 1] - l0 : g->n;
         a.leaf0 = l0 << h->ts;
         a.nleaf = nl << h->ts;
         if (a.nleaf == 0) continue;
@@ -401,7 +410,7 @@ int load_table(hydro_t *h, const char *path) {
         const size_t colon = t.find(':', c);
         char *end = nullptr;
         const long v = colon == std::string::npos ? -2 : strtol(t.c_str() + colon + 1, &end, 10);
-        if (v < -1 || v > HYDRO_SCHED_TILED || v == HYDRO_SCHED_AUTO)
+        if (v < -1 || v == HYDRO_SCHED_AUTO || (v > HYDRO_SCHED_TILED && v != MULTI_MERGE))
             return fail(h, HYDRO_EINVAL, "bad concurrent schedule in tune cache");
         h->multi_sched = (int32_t)v;
     }
@@ -885,9 +894,9 @@ int hydro_autotune(hydro_t *h, const hydro_grid *g, const char *cache_path, int3
         hydro_grid part = *g;
         part.n_reflux = 0;
         h->p.schedule = HYDRO_SCHED_AUTO;
-        constexpr int NCAND = 4, ROUNDS = 2, REPS = 3;
-        const int cand[NCAND] = {-1, HYDRO_SCHED_COLUMN, HYDRO_SCHED_PERSISTENT, HYDRO_SCHED_TILED};
-        float cand_ms[NCAND] = {1e30f, 1e30f, 1e30f, 1e30f};
+        constexpr int NCAND = 5, ROUNDS = 2, REPS = 3;
+        const int cand[NCAND] = {-1, HYDRO_SCHED_COLUMN, HYDRO_SCHED_PERSISTENT, HYDRO_SCHED_TILED, MULTI_MERGE};
+        float cand_ms[NCAND] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
         for (int round = 0; round < ROUNDS && rc == HYDRO_OK; ++round) {
             for (int ci = 0; ci < NCAND && rc == HYDRO_OK; ++ci) {
                 h->multi_sched = cand[ci];
