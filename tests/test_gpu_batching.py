@@ -268,3 +268,34 @@ def test_autotune_concurrent_partition(torch, tmp_path):
     finally:
         tuned.close()
         col.close()
+
+
+def test_aggregated_launch_is_bitwise_the_partitioned_step(torch, tmp_path):
+    # a tune cache whose choice for stages of several launches is one launch
+    # over the whole partition (the tuner's aggregation): each stage is then a
+    # single launch, and the step is bit for bit the step of the six
+    # concurrent launches
+    from paper_2107_10987_amd.hydro import Hydro
+    print("case: the polytrope's uneven partition as one launch per stage", flush=True)
+    w = rotating_polytrope()
+    off = uneven_batches(w.n)
+    path = os.path.join(tmp_path, "merge.json")
+    with open(path, "w") as f:
+        json.dump({"schedule": [2] * 16, "concurrent": 5}, f)
+    merged = Hydro(max_leaves=w.n, schedule="auto", tune_cache=path)
+    col = Hydro(max_leaves=w.n, schedule="column")
+    try:
+        ga = merged.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        gb = col.grid(w.tree, torch.tensor(w.U, device="cuda"), w.omega, w.gamma, launch_off=off)
+        dt = float(w.cfl * np.min(w.tree.dx / col.signal_speed(gb).cpu().numpy()))
+        merged.timing(True)
+        merged.step(ga, dt)
+        _, merged_launches = merged.timing(False)
+        col.timing(True)
+        col.step(gb, dt)
+        _, col_launches = col.timing(False)
+        assert merged_launches == 2 and col_launches == 2 * (len(off) - 1)
+        assert torch.equal(ga.U, gb.U)
+    finally:
+        merged.close()
+        col.close()
