@@ -1167,14 +1167,15 @@ hipError_t hydro_launch_pairs(const double *U, const int32_t *gm, const int32_t 
     return hipGetLastError();
 }
 
-// dt_out = cfl * min over leaves of dx / amax (one workgroup).
-// dt = cfl * min over blocks of dx / a_max (blocks b of leaf b >> ts).
-__global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double *amax, int n, int ts,
-                                                 double cfl, double *dt_out) {
-    __shared__ double red[4];
+// dt = cfl * min over blocks of dx / a_max (blocks b of leaf b >> ts), by
+// one workgroup of 1024 threads (the minimum is exact in any order).
+constexpr int NTDT = 1024;
+__global__ void __launch_bounds__(NTDT) dt_kernel(const double *dx, const double *amax, int n, int ts,
+                                                  double cfl, double *dt_out) {
+    __shared__ double red[NTDT / 64];
     double m = INFINITY;
     const int nb = n << ts;
-    for (int b = threadIdx.x; b < nb; b += 256) {
+    for (int b = threadIdx.x; b < nb; b += NTDT) {
         const double v = dx[b >> ts] / amax[b];
         m = v < m ? v : m;
     }
@@ -1187,7 +1188,7 @@ __global__ void __launch_bounds__(256) dt_kernel(const double *dx, const double 
     __syncthreads();
     if (threadIdx.x == 0) {
         double r = red[0];
-        for (int w = 1; w < 4; ++w) r = red[w] < r ? red[w] : r;
+        for (int w = 1; w < NTDT / 64; ++w) r = red[w] < r ? red[w] : r;
         *dt_out = cfl * r;
     }
 }
@@ -1200,7 +1201,7 @@ hipError_t hydro_launch_reflux(const RefluxArgs &r, int n_entries, hipStream_t s
 
 hipError_t hydro_launch_dt(const double *dx, const double *amax, int n, int ts, double cfl,
                            double *dt_out, hipStream_t s) {
-    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, dx, amax, n, ts, cfl, dt_out);
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(NTDT), 0, s, dx, amax, n, ts, cfl, dt_out);
     return hipGetLastError();
 }
 
