@@ -6,26 +6,16 @@ the anisotropy of the shock (its radius along a body diagonal against its
 radius along a coordinate axis; a grid-aligned error shows there).  Both
 schemes conserve mass and energy to round-off; the comparison is printed and
 kept in the design notes."""
-import numpy as np
 import pytest
 
-import sedov_similarity as ss
+import sedov_metrics as sm
 from paper_2107_10987_amd.workloads import sedov_uniform
-
-
-def _exact_density(r, R, gamma):
-    lam, (U, G, P) = ss.solve(gamma)
-    order = np.argsort(lam)
-    x = r / R
-    inside = np.interp(x, lam[order], G[order])
-    return np.where(x < 1.0, inside, 1.0)
 
 
 def _run(oracle_mod, centre_only, R_target=0.3):
     w = sedov_uniform(4)
     o = oracle_mod.Oracle(w.tree, w.gamma, 0.0, centre_only=centre_only)
-    xi = ss.xi0(w.gamma)
-    t_end = (R_target / xi) ** 2.5
+    t_end = sm.end_time(R_target, w.gamma)
     U, t, steps = w.U, 0.0, 0
     M0 = U[:, 0].sum()
     E0 = U[:, 4].sum()
@@ -36,33 +26,9 @@ def _run(oracle_mod, centre_only, R_target=0.3):
         steps += 1
     assert abs(U[:, 0].sum() - M0) <= 1e-13 * M0
     assert abs(U[:, 4].sum() - E0) <= 1e-13 * E0
-    xc = w.tree.cell_centres()                                # [n, 3, 8, 8, 8]
-    r = np.sqrt((xc ** 2).sum(axis=1)).ravel()
-    rho = U[:, 0].ravel()
-    ex = _exact_density(r, R_target, w.gamma)
-    l1 = np.abs(rho - ex).sum() / ex.sum()
-    # radial profile peak
-    dx = w.tree.dx0
-    edges = np.arange(0.0, 0.5, dx)
-    idx = np.digitize(r, edges)
-    prof = np.array([rho[idx == i].mean() for i in range(1, len(edges))])
-    rc = 0.5 * (edges[1:] + edges[:-1])
-    r_peak = rc[np.argmax(prof)]
-    # along the +x axis (the cells next to it) and along the body diagonal
-    X = xc[:, 0].ravel()
-    Y = xc[:, 1].ravel()
-    Z = xc[:, 2].ravel()
-    h = 0.5 * dx + 1e-12
-    axis = (np.abs(Y) <= h) & (np.abs(Z) <= h) & (X > 0)
-    diag = (np.abs(X - Y) <= 1e-12) & (np.abs(X - Z) <= 1e-12) & (X > 0)
-    r_axis = r[axis][np.argmax(rho[axis])]
-    r_diag = r[diag][np.argmax(rho[diag])]
-    # angular scatter: relative spread of the density over each radial shell
-    # within 0.25 R of the shock, mean over those shells
-    shells = [i for i in range(1, len(edges)) if abs(rc[i - 1] - R_target) <= 0.25 * R_target]
-    scatter = float(np.mean([rho[idx == i].std() / rho[idx == i].mean() for i in shells]))
-    return dict(l1=l1, r_peak=r_peak, r_axis=r_axis, r_diag=r_diag, rho_max=rho.max(), steps=steps,
-                R=R_target, rho_axis=rho[axis].max(), rho_diag=rho[diag].max(), scatter=scatter)
+    d = sm.metrics(w.tree, U, R_target, w.gamma)
+    d["steps"] = steps
+    return d
 
 
 @pytest.mark.slow
@@ -70,10 +36,7 @@ def test_old_and_new_scheme_accuracy_on_sedov(oracle_mod):
     new = _run(oracle_mod, False)
     old = _run(oracle_mod, True)
     for name, d in (("new (9 points per face)", new), ("old (face centre)", old)):
-        print(f"{name}: density L1 {d['l1']:.4f}; shock radius {d['r_peak']:.4f} (exact {d['R']}); "
-              f"peak along axis {d['r_axis']:.4f} / diagonal {d['r_diag']:.4f}, peak density there "
-              f"{d['rho_axis']:.3f} / {d['rho_diag']:.3f}; shell scatter {d['scatter']:.4f}; "
-              f"peak density {d['rho_max']:.3f}; {d['steps']} steps", flush=True)
+        print(sm.describe(name, d, d["steps"]), flush=True)
     for d in (new, old):
         assert abs(d["r_peak"] - d["R"]) <= 0.05 * d["R"]
         assert d["rho_max"] <= 4.0
